@@ -1,0 +1,164 @@
+/*
+ * psfs.h -- C ABI of the MI355X (gfx950) probabilistic shape-from-silhouette
+ * occupancy library.
+ *
+ * The method (Song, Bian et al., "Digitize Your Body and Action in 3-D at Over
+ * 10 FPS", Sec. 2.2.2):
+ *   - Eq. 1-2: every pixel of every view gets a silhouette likelihood
+ *     SLM = P(F=1 | I) from a per-pixel single-Gaussian background model
+ *     N(I | mu, var) against a uniform foreground density u, with equal priors.
+ *   - Eq. 3-9: every voxel of a regular grid gets the occupancy posterior
+ *     P(V=1 | {S}) by fusing, over the views, the SLM value at the pixel its
+ *     centre projects to, with a latent occluder summed out. Summed out with
+ *     P(O)=1/2, Eq. 5-9 say that each view that sees the voxel multiplies the
+ *     prior odds by 2*SLM; the library evaluates exactly that, in FP32 in the
+ *     log domain: logit P = logit(prior) + sum_k log(2*SLM_k).
+ *   - Sec. 2.2.2 (last step): the posterior is thresholded to an occupancy grid.
+ *
+ * Conventions (all functions):
+ *   - Memory: the caller owns every device buffer and the stream. The library
+ *     copies host structs, borrows device pointers until the enqueued work has
+ *     passed on the stream, and allocates no device memory except inside a
+ *     batch object (its device descriptor table, see psfs_batch_create).
+ *     Scratch lives in a caller-provided workspace whose size the library
+ *     reports.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream). Every compute call is asynchronous; faults surface at the
+ *     caller's synchronisation.
+ *   - Errors: every `int` function returns a psfs_status. Arguments are
+ *     validated before anything is enqueued; on an error nothing is enqueued
+ *     and psfs_last_error() holds a thread-local message. HIP runtime failures
+ *     return PSFS_E_HIP. No C++ exception crosses this ABI.
+ *   - Threads: a plan or batch is not thread-safe; distinct ones are.
+ *   - Layouts: images are u8 RGB [H][W][3]; background mean and variance are
+ *     FP32 [H][W][3]; a camera matrix P is FP32 row-major 3x4 mapping world
+ *     metres (homogeneous) to pixels, with pixel centres at integer
+ *     coordinates; voxel grids are [nz][ny][nx] with x fastest and voxel
+ *     (i,j,k) centred at origin + voxel * (i+1/2, j+1/2, k+1/2).
+ *   - Alignment: mean, var, likelihood-map and posterior pointers must be
+ *     16-byte aligned, image pointers 4-byte aligned (PSFS_E_ARG otherwise).
+ */
+#ifndef PSFS_H
+#define PSFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSFS_VERSION 1
+#define PSFS_MAX_VIEWS 16
+
+enum psfs_status {
+    PSFS_OK = 0,
+    PSFS_E_ARG = -1,        /* null/misaligned pointer, bad enum value */
+    PSFS_E_RANGE = -2,      /* a size or value outside its documented range */
+    PSFS_E_NOT_READY = -3,  /* cameras, grid or a background not set yet */
+    PSFS_E_WORKSPACE = -4,  /* workspace missing or smaller than required */
+    PSFS_E_HIP = -5,        /* HIP runtime error; text in psfs_last_error() */
+    PSFS_E_DEVICE = -6,     /* the current device is not a gfx950 GPU */
+    PSFS_E_STALE = -7       /* batch update changes the captured shapes */
+};
+
+enum psfs_sampling {
+    PSFS_NEAREST = 0,       /* pixel x = floor(u + 1/2), y = floor(v + 1/2) (Eq. 3-9) */
+    PSFS_BILINEAR = 1       /* log(2*SLM) interpolated from taps floor(u)+{0,1},
+                               floor(v)+{0,1}; taps outside the image count 0 */
+};
+
+/* One view: image size and the 3x4 projection (u*c, v*c, c) = P [X; 1].
+ * A voxel is seen by the view when c > 0 and its pixel lies in the image. */
+typedef struct psfs_camera {
+    int32_t width, height;  /* 1..65535 each, width*height < 2^31 */
+    float P[12];            /* row-major 3x4, finite */
+} psfs_camera;
+
+/* Regular voxel grid; any dimension may be 0 (an empty grid: calls are no-ops).
+ * nx*ny*nz < 2^31. */
+typedef struct psfs_grid {
+    int32_t nx, ny, nz;
+    float origin[3];        /* corner of voxel (0,0,0), metres */
+    float voxel;            /* edge length, > 0 */
+} psfs_grid;
+
+/* Model parameters (defaults from psfs_default_params):
+ *   prior      P(V=1) in Eq. 3, in (0,1); default 1/2
+ *   log_u      log of the uniform foreground density of Eq. 1; default
+ *              -3*ln(256) (uniform over the 8-bit RGB cube); finite
+ *   threshold  occupancy = (posterior > threshold), in [0,1]; default 1/2
+ *   sampling   psfs_sampling used by psfs_fuse/psfs_reconstruct */
+typedef struct psfs_params {
+    float prior;
+    float log_u;
+    float threshold;
+    int32_t sampling;
+} psfs_params;
+
+typedef struct psfs_plan psfs_plan;     /* opaque, host-only */
+
+int psfs_version(void);
+const char *psfs_status_str(int status);
+/* Thread-local text of the last failing call on this thread ("" if none). */
+const char *psfs_last_error(void);
+void psfs_default_params(psfs_params *out);
+
+/* ---------------------------------------------------------------- plans */
+
+int psfs_plan_create(psfs_plan **out);
+void psfs_plan_destroy(psfs_plan *plan);                 /* NULL-safe */
+
+/* Copies n (0..PSFS_MAX_VIEWS) cameras. Forgets every background set before. */
+int psfs_set_cameras(psfs_plan *plan, int n, const psfs_camera *cams);
+int psfs_set_grid(psfs_plan *plan, const psfs_grid *grid);
+int psfs_set_params(psfs_plan *plan, const psfs_params *params);
+/* Background model of view `view` (Eq. 1): borrowed device pointers to FP32
+ * [H][W][3] means and variances (variances > 0 and finite; the kernels do not
+ * re-check). The caller keeps them alive while work that reads them runs. */
+int psfs_set_background(psfs_plan *plan, int view, const float *mean_dev, const float *var_dev);
+
+/* Likelihood-map layout: view k occupies floats [offset(k), offset(k) + W_k*H_k)
+ * of one buffer, offsets padded to multiples of 64 floats. Returns the total
+ * number of floats / the offset of view k, or a negative psfs_status. */
+int64_t psfs_lmap_floats(const psfs_plan *plan);
+int64_t psfs_lmap_offset(const psfs_plan *plan, int view);
+
+/* Workspace of psfs_reconstruct: the likelihood maps. 0 if cameras unset. */
+size_t psfs_workspace_bytes(const psfs_plan *plan);
+
+/* ------------------------------------------------------- forward pass */
+
+/* Eq. 1-2 for every view: lmap[offset(k) + y*W_k + x] = log(2*SLM) of pixel
+ * (x, y) of view k, FP32. images_dev: host array of n device pointers. */
+int psfs_likelihood(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap_dev,
+                    void *stream);
+
+/* Eq. 3-9 from likelihood maps in the psfs_lmap_* layout: posterior FP32
+ * [nz][ny][nx]; occ (nullable) u8 [nz][ny][nx] = posterior > threshold.
+ * Sampling per params (nearest by default; bilinear gives the posterior of the
+ * differentiable variant). */
+int psfs_fuse(psfs_plan *plan, const float *lmap_dev, float *posterior_dev, uint8_t *occ_dev,
+              void *stream);
+
+/* psfs_likelihood into the workspace, then psfs_fuse. */
+int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev,
+                     uint8_t *occ_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* occ[i] = posterior[i] > tau for i < nvox (Sec. 2.2.2 thresholding);
+ * tau in [0,1]; nvox >= 0. */
+int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,
+                   void *stream);
+
+/* Kernel variant selection used by the batch and forward paths:
+ * tile = index into the library's fusion tile table (see psfs_tile_count),
+ * or -1 for the tuned/default choice. */
+int psfs_tile_count(void);
+int psfs_tile_describe(int tile, int32_t *tx, int32_t *ty, int32_t *kz);
+int psfs_set_tile(psfs_plan *plan, int tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSFS_H */

@@ -1,0 +1,198 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Torch provides device memory and the stream: every tensor passed here must be
+a contiguous tensor on the current GPU with the documented dtype; all compute
+runs in the library's HIP kernels, enqueued on
+``torch.cuda.current_stream()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+LOG_U_DEFAULT = -3.0 * math.log(256.0)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def make_camera(width: int, height: int, P) -> L.psfs_camera:
+    c = L.psfs_camera()
+    c.width, c.height = int(width), int(height)
+    flat = np.asarray(P, np.float32).reshape(12)
+    for e in range(12):
+        c.P[e] = float(flat[e])
+    return c
+
+
+def make_grid(nx, ny, nz, origin, voxel) -> L.psfs_grid:
+    g = L.psfs_grid()
+    g.nx, g.ny, g.nz = int(nx), int(ny), int(nz)
+    o = np.asarray(origin, np.float32).reshape(3)
+    for d in range(3):
+        g.origin[d] = float(o[d])
+    g.voxel = float(np.float32(voxel))
+    return g
+
+
+def threshold(posterior: torch.Tensor, tau: float = 0.5, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    occ = out if out is not None else torch.empty(posterior.shape, dtype=torch.uint8, device=posterior.device)
+    L.check(L.lib().psfs_threshold(_dev(posterior, torch.float32, "posterior"), posterior.numel(), float(tau),
+                                   _dev(occ, torch.uint8, "occ", posterior.shape), _stream()))
+    return occ
+
+
+class Plan:
+    """A reconstruction plan: cameras, grid, parameters and background model.
+
+    ``cams``: objects with ``width``, ``height`` and a 3x4 ``P`` (FP32).
+    ``grid``: object with ``nx, ny, nz, origin, voxel``.
+    """
+
+    def __init__(self, cams=None, grid=None, prior=0.5, log_u=LOG_U_DEFAULT, threshold=0.5,
+                 sampling: int = L.NEAREST):
+        h = C.c_void_p()
+        L.check(L.lib().psfs_plan_create(C.byref(h)))
+        self._h = h
+        self._keep = {}
+        self.cams = []
+        self.grid = None
+        self.set_params(prior, log_u, threshold, sampling)
+        if cams is not None:
+            self.set_cameras(cams)
+        if grid is not None:
+            self.set_grid(grid)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib().psfs_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -------------------------------------------------------------- setup
+    def set_cameras(self, cams: Sequence) -> None:
+        arr = (L.psfs_camera * max(len(cams), 1))(*[make_camera(c.width, c.height, c.P) for c in cams])
+        L.check(L.lib().psfs_set_cameras(self._h, len(cams), arr))
+        self.cams = list(cams)
+        self._keep = {k: v for k, v in self._keep.items() if not k.startswith("bg")}
+
+    def set_grid(self, grid) -> None:
+        g = make_grid(grid.nx, grid.ny, grid.nz, grid.origin, grid.voxel)
+        L.check(L.lib().psfs_set_grid(self._h, C.byref(g)))
+        self.grid = grid
+
+    def set_params(self, prior=0.5, log_u=LOG_U_DEFAULT, threshold=0.5, sampling: int = L.NEAREST) -> None:
+        p = L.psfs_params(float(prior), float(log_u), float(threshold), int(sampling))
+        L.check(L.lib().psfs_set_params(self._h, C.byref(p)))
+        self.params = p
+
+    def set_tile(self, tile: int) -> None:
+        L.check(L.lib().psfs_set_tile(self._h, int(tile)))
+
+    def set_background(self, view: int, mean: torch.Tensor, var: torch.Tensor) -> None:
+        c = self.cams[view]
+        shape = (c.height, c.width, 3)
+        mp = _dev(mean, torch.float32, "mean", shape)
+        vp_ = _dev(var, torch.float32, "var", shape)
+        L.check(L.lib().psfs_set_background(self._h, int(view), mp, vp_))
+        self._keep[f"bg{view}"] = (mean, var)
+
+    def set_backgrounds(self, means: Sequence[torch.Tensor], vars_: Sequence[torch.Tensor]) -> None:
+        for k, (m, v) in enumerate(zip(means, vars_)):
+            self.set_background(k, m, v)
+
+    # --------------------------------------------------------- buffers
+    @property
+    def n(self) -> int:
+        return len(self.cams)
+
+    def lmap_floats(self) -> int:
+        return L.check(L.lib().psfs_lmap_floats(self._h))
+
+    def lmap_offset(self, view: int) -> int:
+        return L.check(L.lib().psfs_lmap_offset(self._h, int(view)))
+
+    def workspace_bytes(self) -> int:
+        return int(L.lib().psfs_workspace_bytes(self._h))
+
+    def new_workspace(self, nbytes: Optional[int] = None) -> torch.Tensor:
+        n = self.workspace_bytes() if nbytes is None else nbytes
+        return torch.empty(max(n, 16), dtype=torch.uint8, device="cuda")
+
+    def _images(self, images: Sequence[torch.Tensor]):
+        if len(images) != self.n:
+            raise ValueError(f"expected {self.n} images, got {len(images)}")
+        ptrs = [_dev(im, torch.uint8, f"images[{k}]", (c.height, c.width, 3))
+                for k, (im, c) in enumerate(zip(images, self.cams))]
+        return L.ptr_array(ptrs)
+
+    def lmap_view(self, lmap: torch.Tensor, view: int) -> torch.Tensor:
+        c = self.cams[view]
+        off = self.lmap_offset(view)
+        return lmap[off:off + c.width * c.height].view(c.height, c.width)
+
+    # --------------------------------------------------------- compute
+    def likelihood(self, images: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Eq. 1-2: log(2*SLM) maps of all views in one buffer (psfs_lmap_* layout)."""
+        lmap = out if out is not None else torch.empty(max(self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
+        L.check(L.lib().psfs_likelihood(self._h, self._images(images), _dev(lmap, torch.float32, "lmap"), _stream()))
+        return lmap
+
+    def _outputs(self, posterior, occ, want_occ):
+        g = self.grid
+        shape = (g.nz, g.ny, g.nx)
+        post = posterior if posterior is not None else torch.empty(shape, dtype=torch.float32, device="cuda")
+        if want_occ and occ is None:
+            occ = torch.empty(shape, dtype=torch.uint8, device="cuda")
+        pp = _dev(post, torch.float32, "posterior", shape)
+        op = _dev(occ, torch.uint8, "occ", shape) if occ is not None else None
+        return post, occ, pp, op
+
+    def fuse(self, lmap: torch.Tensor, posterior=None, occ=None, want_occ=True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+        """Eq. 3-9 (+ threshold) from likelihood maps."""
+        post, occ, pp, op = self._outputs(posterior, occ, want_occ)
+        L.check(L.lib().psfs_fuse(self._h, _dev(lmap, torch.float32, "lmap"), pp, op, _stream()))
+        return post, occ
+
+    def reconstruct(self, images: Sequence[torch.Tensor], posterior=None, occ=None, workspace=None,
+                    want_occ=True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+        """Likelihood maps + fusion + threshold for one frame."""
+        ims = self._images(images)
+        post, occ, pp, op = self._outputs(posterior, occ, want_occ)
+        ws = workspace if workspace is not None else self.new_workspace()
+        L.check(L.lib().psfs_reconstruct(self._h, ims, pp, op, _dev(ws, torch.uint8, "workspace"),
+                                         ws.numel(), _stream()))
+        return post, occ
+
+
+def tiles():
+    n = L.lib().psfs_tile_count()
+    out = []
+    for t in range(n):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.lib().psfs_tile_describe(t, C.byref(a), C.byref(b), C.byref(c)))
+        out.append((a.value, b.value, c.value))
+    return out

@@ -1,0 +1,408 @@
+// Host side of libpsfs: plans, argument validation, workspace layout and
+// kernel launches behind the C ABI of psfs.h. Every entry point validates its
+// arguments before enqueueing anything and never lets an exception escape.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "psfs_internal.h"
+
+struct psfs_plan {
+    int n = -1;                                     // -1: cameras not set
+    psfs_camera cams[PSFS_MAX_VIEWS];
+    bool has_grid = false;
+    psfs_grid grid{};
+    psfs_params params{};
+    const float *mean[PSFS_MAX_VIEWS] = {};
+    const float *var[PSFS_MAX_VIEWS] = {};
+    int tile = -1;
+};
+
+namespace psfs {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(PSFS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool finite_all(const float *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// Per-device check that the current device is gfx950 (cached).
+int check_device()
+{
+    static std::mutex mu;
+    static signed char state[256] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 256) return fail(PSFS_E_DEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (state[dev] == 1) return PSFS_OK;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        state[dev] = -1;
+        return fail(PSFS_E_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    }
+    state[dev] = 1;
+    return PSFS_OK;
+}
+
+int64_t map_floats(const psfs_plan *p)
+{
+    int64_t total = 0;
+    for (int k = 0; k < p->n; ++k) {
+        const int64_t np = static_cast<int64_t>(p->cams[k].width) * p->cams[k].height;
+        total += (np + kMapAlignFloats - 1) / kMapAlignFloats * kMapAlignFloats;
+    }
+    return total;
+}
+
+int64_t map_offset(const psfs_plan *p, int view)
+{
+    int64_t off = 0;
+    for (int k = 0; k < view; ++k) {
+        const int64_t np = static_cast<int64_t>(p->cams[k].width) * p->cams[k].height;
+        off += (np + kMapAlignFloats - 1) / kMapAlignFloats * kMapAlignFloats;
+    }
+    return off;
+}
+
+int64_t nvox(const psfs_grid &g) { return static_cast<int64_t>(g.nx) * g.ny * g.nz; }
+
+int need_cameras(const psfs_plan *p)
+{
+    if (!p) return fail(PSFS_E_ARG, "plan is NULL");
+    if (p->n < 0) return fail(PSFS_E_NOT_READY, "cameras not set");
+    return PSFS_OK;
+}
+
+int need_backgrounds(const psfs_plan *p)
+{
+    int rc = need_cameras(p);
+    if (rc) return rc;
+    for (int k = 0; k < p->n; ++k)
+        if (!p->mean[k] || !p->var[k]) return fail(PSFS_E_NOT_READY, "background of view %d not set", k);
+    return PSFS_OK;
+}
+
+int need_grid(const psfs_plan *p)
+{
+    int rc = need_cameras(p);
+    if (rc) return rc;
+    if (!p->has_grid) return fail(PSFS_E_NOT_READY, "grid not set");
+    return PSFS_OK;
+}
+
+int check_images(const psfs_plan *p, const uint8_t *const *images)
+{
+    if (p->n > 0 && !images) return fail(PSFS_E_ARG, "images array is NULL");
+    for (int k = 0; k < p->n; ++k) {
+        if (!images[k]) return fail(PSFS_E_ARG, "image of view %d is NULL", k);
+        if (!aligned(images[k], 4)) return fail(PSFS_E_ARG, "image of view %d is not 4-byte aligned", k);
+    }
+    return PSFS_OK;
+}
+
+int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *lmap, hipStream_t s)
+{
+    if (p->n == 0) return PSFS_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    SlmArgs a{};
+    a.n = p->n;
+    a.lmap = lmap;
+    a.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(p->params.log_u));
+    int64_t max_np = 0;
+    for (int k = 0; k < p->n; ++k) {
+        const int64_t np = static_cast<int64_t>(p->cams[k].width) * p->cams[k].height;
+        a.view[k] = SlmView{images[k], p->mean[k], p->var[k], np, map_offset(p, k)};
+        if (np > max_np) max_np = np;
+    }
+    hipError_t e = launch_slm(a, max_np, s);
+    if (e != hipSuccess) return hip_fail(e, "likelihood kernel launch");
+    return PSFS_OK;
+}
+
+void fill_geometry(const psfs_plan *p, int sampling, FuseArgs &a)
+{
+    a.n = p->n;
+    for (int k = 0; k < p->n; ++k) {
+        ViewGeom &g = a.view[k];
+        const float *P = p->cams[k].P;
+        for (int e = 0; e < 12; ++e) g.P[e] = P[e];
+        if (sampling == PSFS_NEAREST) {
+            // floor((row0 + row2/2).X / row2.X) = floor(u + 1/2)
+            for (int c = 0; c < 4; ++c) {
+                g.P[c] = static_cast<float>(static_cast<double>(P[c]) + 0.5 * P[8 + c]);
+                g.P[4 + c] = static_cast<float>(static_cast<double>(P[4 + c]) + 0.5 * P[8 + c]);
+            }
+        }
+        g.W = p->cams[k].width;
+        g.H = p->cams[k].height;
+        g.map_off = map_offset(p, k);
+    }
+    a.nx = p->grid.nx;
+    a.ny = p->grid.ny;
+    a.nz = p->grid.nz;
+    a.ox = p->grid.origin[0];
+    a.oy = p->grid.origin[1];
+    a.oz = p->grid.origin[2];
+    a.h = p->grid.voxel;
+    const double pr = p->params.prior;
+    a.L0 = static_cast<float>(std::log(pr / (1.0 - pr)));
+    a.tau = p->params.threshold;
+}
+
+int enqueue_fuse(const psfs_plan *p, const float *lmap, float *post, uint8_t *occ, hipStream_t s)
+{
+    if (nvox(p->grid) == 0) return PSFS_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    FuseArgs a{};
+    fill_geometry(p, p->params.sampling, a);
+    a.lmap = lmap;
+    a.post = post;
+    a.occ = occ;
+    const int tile = p->tile >= 0 ? p->tile : default_tile();
+    hipError_t e = launch_fuse(a, tile, p->params.sampling, s);
+    if (e != hipSuccess) return hip_fail(e, "fusion kernel launch");
+    return PSFS_OK;
+}
+
+}  // namespace
+}  // namespace psfs
+
+using namespace psfs;
+
+#define PSFS_GUARD_BEGIN try {
+#define PSFS_GUARD_END                                                    \
+    }                                                                     \
+    catch (const std::bad_alloc &) { return fail(PSFS_E_RANGE, "out of host memory"); } \
+    catch (...) { return fail(PSFS_E_ARG, "unexpected exception"); }
+
+extern "C" {
+
+int psfs_version(void) { return PSFS_VERSION; }
+
+const char *psfs_status_str(int status)
+{
+    switch (status) {
+    case PSFS_OK: return "ok";
+    case PSFS_E_ARG: return "invalid argument";
+    case PSFS_E_RANGE: return "value out of range";
+    case PSFS_E_NOT_READY: return "plan not ready";
+    case PSFS_E_WORKSPACE: return "workspace too small";
+    case PSFS_E_HIP: return "HIP runtime error";
+    case PSFS_E_DEVICE: return "unsupported device";
+    case PSFS_E_STALE: return "batch shape changed";
+    default: return "unknown status";
+    }
+}
+
+const char *psfs_last_error(void) { return g_last_error.c_str(); }
+
+void psfs_default_params(psfs_params *out)
+{
+    if (!out) return;
+    out->prior = 0.5f;
+    out->log_u = static_cast<float>(-3.0 * std::log(256.0));
+    out->threshold = 0.5f;
+    out->sampling = PSFS_NEAREST;
+}
+
+int psfs_plan_create(psfs_plan **out)
+{
+    PSFS_GUARD_BEGIN
+    if (!out) return fail(PSFS_E_ARG, "out is NULL");
+    psfs_plan *p = new psfs_plan();
+    psfs_default_params(&p->params);
+    *out = p;
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
+void psfs_plan_destroy(psfs_plan *plan) { delete plan; }
+
+int psfs_set_cameras(psfs_plan *plan, int n, const psfs_camera *cams)
+{
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (n < 0 || n > PSFS_MAX_VIEWS) return fail(PSFS_E_RANGE, "view count %d outside 0..%d", n, PSFS_MAX_VIEWS);
+    if (n > 0 && !cams) return fail(PSFS_E_ARG, "cams is NULL");
+    for (int k = 0; k < n; ++k) {
+        const psfs_camera &c = cams[k];
+        if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535 ||
+            static_cast<int64_t>(c.width) * c.height >= (int64_t(1) << 31))
+            return fail(PSFS_E_RANGE, "view %d: image size %dx%d out of range", k, c.width, c.height);
+        if (!finite_all(c.P, 12)) return fail(PSFS_E_RANGE, "view %d: camera matrix not finite", k);
+    }
+    plan->n = n;
+    for (int k = 0; k < n; ++k) plan->cams[k] = cams[k];
+    for (int k = 0; k < PSFS_MAX_VIEWS; ++k) plan->mean[k] = plan->var[k] = nullptr;
+    return PSFS_OK;
+}
+
+int psfs_set_grid(psfs_plan *plan, const psfs_grid *g)
+{
+    if (!plan || !g) return fail(PSFS_E_ARG, "plan or grid is NULL");
+    if (g->nx < 0 || g->ny < 0 || g->nz < 0 || nvox(*g) >= (int64_t(1) << 31))
+        return fail(PSFS_E_RANGE, "grid %dx%dx%d out of range", g->nx, g->ny, g->nz);
+    if (!(g->voxel > 0.0f) || !std::isfinite(g->voxel) || !finite_all(g->origin, 3))
+        return fail(PSFS_E_RANGE, "grid voxel size or origin invalid");
+    plan->grid = *g;
+    plan->has_grid = true;
+    return PSFS_OK;
+}
+
+int psfs_set_params(psfs_plan *plan, const psfs_params *prm)
+{
+    if (!plan || !prm) return fail(PSFS_E_ARG, "plan or params is NULL");
+    if (!(prm->prior > 0.0f && prm->prior < 1.0f)) return fail(PSFS_E_RANGE, "prior must lie in (0,1)");
+    if (!std::isfinite(prm->log_u)) return fail(PSFS_E_RANGE, "log_u must be finite");
+    if (!(prm->threshold >= 0.0f && prm->threshold <= 1.0f)) return fail(PSFS_E_RANGE, "threshold must lie in [0,1]");
+    if (prm->sampling != PSFS_NEAREST && prm->sampling != PSFS_BILINEAR)
+        return fail(PSFS_E_ARG, "unknown sampling %d", prm->sampling);
+    plan->params = *prm;
+    return PSFS_OK;
+}
+
+int psfs_set_background(psfs_plan *plan, int view, const float *mean_dev, const float *var_dev)
+{
+    int rc = need_cameras(plan);
+    if (rc) return rc;
+    if (view < 0 || view >= plan->n) return fail(PSFS_E_RANGE, "view %d outside 0..%d", view, plan->n - 1);
+    if (!mean_dev || !var_dev) return fail(PSFS_E_ARG, "background pointer is NULL");
+    if (!aligned(mean_dev, 16) || !aligned(var_dev, 16)) return fail(PSFS_E_ARG, "background pointers must be 16-byte aligned");
+    plan->mean[view] = mean_dev;
+    plan->var[view] = var_dev;
+    return PSFS_OK;
+}
+
+int64_t psfs_lmap_floats(const psfs_plan *plan)
+{
+    int rc = need_cameras(plan);
+    if (rc) return rc;
+    return map_floats(plan);
+}
+
+int64_t psfs_lmap_offset(const psfs_plan *plan, int view)
+{
+    int rc = need_cameras(plan);
+    if (rc) return rc;
+    if (view < 0 || view >= plan->n) return fail(PSFS_E_RANGE, "view %d outside 0..%d", view, plan->n - 1);
+    return map_offset(plan, view);
+}
+
+size_t psfs_workspace_bytes(const psfs_plan *plan)
+{
+    if (!plan || plan->n < 0) return 0;
+    return static_cast<size_t>(map_floats(plan)) * sizeof(float);
+}
+
+int psfs_likelihood(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_backgrounds(plan);
+    if (rc) return rc;
+    if ((rc = check_images(plan, images_dev))) return rc;
+    if (plan->n > 0 && (!lmap_dev || !aligned(lmap_dev, 16))) return fail(PSFS_E_ARG, "lmap must be a 16-byte aligned device pointer");
+    return enqueue_likelihood(plan, images_dev, lmap_dev, static_cast<hipStream_t>(stream));
+    PSFS_GUARD_END
+}
+
+int psfs_fuse(psfs_plan *plan, const float *lmap_dev, float *posterior_dev, uint8_t *occ_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_grid(plan);
+    if (rc) return rc;
+    if (nvox(plan->grid) > 0) {
+        if (!posterior_dev || !aligned(posterior_dev, 16)) return fail(PSFS_E_ARG, "posterior must be a 16-byte aligned device pointer");
+        if (plan->n > 0 && (!lmap_dev || !aligned(lmap_dev, 16))) return fail(PSFS_E_ARG, "lmap must be a 16-byte aligned device pointer");
+    }
+    return enqueue_fuse(plan, lmap_dev, posterior_dev, occ_dev, static_cast<hipStream_t>(stream));
+    PSFS_GUARD_END
+}
+
+int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev, uint8_t *occ_dev,
+                     void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_backgrounds(plan);
+    if (rc) return rc;
+    if ((rc = need_grid(plan))) return rc;
+    if ((rc = check_images(plan, images_dev))) return rc;
+    if (nvox(plan->grid) > 0 && (!posterior_dev || !aligned(posterior_dev, 16)))
+        return fail(PSFS_E_ARG, "posterior must be a 16-byte aligned device pointer");
+    const size_t need = psfs_workspace_bytes(plan);
+    if (need > 0 && (!workspace_dev || workspace_bytes < need || !aligned(workspace_dev, 16)))
+        return fail(PSFS_E_WORKSPACE, "workspace needs %zu bytes, 16-byte aligned (got %zu)", need, workspace_bytes);
+    if (nvox(plan->grid) == 0) return PSFS_OK;
+    float *lmap = static_cast<float *>(workspace_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = enqueue_likelihood(plan, images_dev, lmap, s))) return rc;
+    return enqueue_fuse(plan, lmap, posterior_dev, occ_dev, s);
+    PSFS_GUARD_END
+}
+
+int psfs_threshold(const float *posterior_dev, int64_t nvox_, float tau, uint8_t *occ_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    if (nvox_ < 0) return fail(PSFS_E_RANGE, "nvox must be >= 0");
+    if (!(tau >= 0.0f && tau <= 1.0f)) return fail(PSFS_E_RANGE, "tau must lie in [0,1]");
+    if (nvox_ == 0) return PSFS_OK;
+    if (!posterior_dev || !occ_dev) return fail(PSFS_E_ARG, "posterior or occ is NULL");
+    int rc = check_device();
+    if (rc) return rc;
+    hipError_t e = launch_threshold(posterior_dev, nvox_, tau, occ_dev, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "threshold kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
+int psfs_tile_count(void) { return tile_count(); }
+
+int psfs_tile_describe(int tile, int32_t *tx, int32_t *ty, int32_t *kz)
+{
+    if (tile < 0 || tile >= tile_count()) return fail(PSFS_E_RANGE, "tile %d outside 0..%d", tile, tile_count() - 1);
+    const TileCfg &c = tile_cfg(tile);
+    if (tx) *tx = c.tx;
+    if (ty) *ty = c.ty;
+    if (kz) *kz = c.kz;
+    return PSFS_OK;
+}
+
+int psfs_set_tile(psfs_plan *plan, int tile)
+{
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (tile < -1 || tile >= tile_count()) return fail(PSFS_E_RANGE, "tile %d outside -1..%d", tile, tile_count() - 1);
+    plan->tile = tile;
+    return PSFS_OK;
+}
+
+}  // extern "C"

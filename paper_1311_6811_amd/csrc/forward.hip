@@ -1,0 +1,248 @@
+// Forward kernels of the occupancy pass for gfx950:
+//   slm_kernel        Eq. 1-2, per-pixel log(2*SLM) map of every view
+//   fuse_kernel       Eq. 3-9, projection + gather + log-domain fusion +
+//                     posterior + threshold (nearest or bilinear sampling)
+//   threshold_kernel  Sec. 2.2.2 thresholding of an existing posterior
+//
+// Log-domain form used throughout: with P(O)=1/2 the occluder sum of Eq. 5-9
+// gives P(S_k|V=1) = SLM_k and P(S_k|V=0) = 1/2, so each view that sees a voxel
+// adds log(2*SLM_k) to the logit of Eq. 3. With SLM = u/(u+N) (Eq. 1-2, equal
+// pixel priors), log(2*SLM) = log 2 - softplus(log N - log u).
+#include "psfs_internal.h"
+
+namespace psfs {
+
+namespace {
+
+constexpr float kLn2 = 0.693147180559945309f;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// log(2*SLM) of one pixel. k0 = -1.5*log(2*pi) - log_u, so that
+// log N - log u = k0 - 1/2 * (sum_c d_c^2/v_c + log(v0*v1*v2)).
+__device__ __forceinline__ float log2slm(float i0, float i1, float i2, float m0, float m1, float m2,
+                                         float v0, float v1, float v2, float k0)
+{
+    const float d0 = i0 - m0, d1 = i1 - m1, d2 = i2 - m2;
+    const float q = d0 * d0 / v0 + d1 * d1 / v1 + d2 * d2 / v2;
+    const float half_logdet = 0.5f * (logf(v0 * v1) + logf(v2));
+    const float d = (k0 - half_logdet) - 0.5f * q;
+    const float softplus = fmaxf(d, 0.0f) + log1pf(expf(-fabsf(d)));
+    return kLn2 - softplus;
+}
+
+__device__ __forceinline__ float byte_of(uint32_t w, int b)
+{
+    return static_cast<float>((w >> (8 * b)) & 0xffu);
+}
+
+// One lane converts 4 consecutive pixels: 12 image bytes (3 dwords) and 12
+// floats each of mean and variance (3 x 16 B), all naturally aligned.
+__global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
+{
+    const SlmView sv = a.view[blockIdx.y];
+    const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
+    if (p0 >= sv.npix) return;
+    float *out = a.lmap + sv.map_off + p0;
+    if (p0 + 4 <= sv.npix) {
+        const uint32_t *iw = reinterpret_cast<const uint32_t *>(sv.img + 3 * p0);
+        const uint32_t w0 = __builtin_nontemporal_load(iw + 0);
+        const uint32_t w1 = __builtin_nontemporal_load(iw + 1);
+        const uint32_t w2 = __builtin_nontemporal_load(iw + 2);
+        const f32x4 *mp = reinterpret_cast<const f32x4 *>(sv.mean + 3 * p0);
+        const f32x4 *vp = reinterpret_cast<const f32x4 *>(sv.var + 3 * p0);
+        const f32x4 m0 = __builtin_nontemporal_load(mp + 0);
+        const f32x4 m1 = __builtin_nontemporal_load(mp + 1);
+        const f32x4 m2 = __builtin_nontemporal_load(mp + 2);
+        const f32x4 v0 = __builtin_nontemporal_load(vp + 0);
+        const f32x4 v1 = __builtin_nontemporal_load(vp + 1);
+        const f32x4 v2 = __builtin_nontemporal_load(vp + 2);
+        f32x4 r;
+        r.x = log2slm(byte_of(w0, 0), byte_of(w0, 1), byte_of(w0, 2), m0.x, m0.y, m0.z, v0.x, v0.y, v0.z, a.k0);
+        r.y = log2slm(byte_of(w0, 3), byte_of(w1, 0), byte_of(w1, 1), m0.w, m1.x, m1.y, v0.w, v1.x, v1.y, a.k0);
+        r.z = log2slm(byte_of(w1, 2), byte_of(w1, 3), byte_of(w2, 0), m1.z, m1.w, m2.x, v1.z, v1.w, v2.x, a.k0);
+        r.w = log2slm(byte_of(w2, 1), byte_of(w2, 2), byte_of(w2, 3), m2.y, m2.z, m2.w, v2.y, v2.z, v2.w, a.k0);
+        *reinterpret_cast<f32x4 *>(out) = r;
+    } else {
+        for (int64_t p = p0; p < sv.npix; ++p) {
+            const uint8_t *I = sv.img + 3 * p;
+            const float *m = sv.mean + 3 * p, *v = sv.var + 3 * p;
+            out[p - p0] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], a.k0);
+        }
+    }
+}
+
+// Bilinear sample of a likelihood map at (x0 + fx, y0 + fy); taps outside the
+// image count 0. x0, y0 are integral doubles (possibly far outside the image).
+__device__ __forceinline__ float bilinear_sample(const float *map, int W, int H, double x0, double y0, float fx, float fy)
+{
+    if (!(x0 >= -1.0 && x0 < W && y0 >= -1.0 && y0 < H)) return 0.0f;
+    const int ix = static_cast<int>(x0), iy = static_cast<int>(y0);
+    const bool xin0 = ix >= 0, xin1 = ix + 1 < W, yin0 = iy >= 0, yin1 = iy + 1 < H;
+    const int64_t base = static_cast<int64_t>(iy) * W + ix;
+    const float l00 = (xin0 && yin0) ? map[base] : 0.0f;
+    const float l10 = (xin1 && yin0) ? map[base + 1] : 0.0f;
+    const float l01 = (xin0 && yin1) ? map[base + W] : 0.0f;
+    const float l11 = (xin1 && yin1) ? map[base + W + 1] : 0.0f;
+    const float top = fmaf(fx, l10 - l00, l00);
+    const float bot = fmaf(fx, l11 - l01, l01);
+    return fmaf(fy, bot - top, top);
+}
+
+// Workgroups are dispatched round-robin over the XCDs; give each XCD one
+// contiguous range of logical blocks (z-slabs of the grid), so that its L2
+// holds one band of rows of every likelihood map.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb)
+{
+    const int64_t per = nb / kNumXcd;
+    if (bid >= per * kNumXcd) return bid;
+    return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+// Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,
+// 64-lane waves are TX x (64/TX) slabs, one voxel thick in z) and KZ
+// consecutive z-slices; each lane owns one column segment of KZ voxels and
+// loops over the views in order k = 0..n-1, so every tile shape produces the
+// same bits. The z-independent part of each projection row is computed once
+// per lane and view.
+template <int TX, int TY, int KZ, int SAMPLING>
+__global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
+{
+    const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
+    const int64_t ntile = static_cast<int64_t>(ntx) * nty;
+    const int64_t nb = ntile * ((a.nz + KZ - 1) / KZ);
+    const int64_t b = xcd_remap(blockIdx.x, nb);
+    const int64_t zc = b / ntile;
+    const int t = static_cast<int>(b - zc * ntile);
+    const int tyi = t / ntx, txi = t - tyi * ntx;
+    const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
+    const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
+    const int k0 = static_cast<int>(zc) * KZ;
+
+    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
+    float Z[KZ], L[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        Z[kk] = a.oz + a.h * (static_cast<float>(k0 + kk) + 0.5f);
+        L[kk] = a.L0;
+    }
+
+    if (SAMPLING == PSFS_NEAREST) {
+        for (int v = 0; v < a.n; ++v) {
+            const ViewGeom &g = a.view[v];
+            const float *map = a.lmap + g.map_off;
+            const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+            const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+            const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float c = fmaf(g.P[10], Z[kk], cx);
+                const float r = __builtin_amdgcn_rcpf(c);
+                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                if (c > 0.0f && static_cast<unsigned>(x) < static_cast<unsigned>(g.W) &&
+                    static_cast<unsigned>(y) < static_cast<unsigned>(g.H))
+                    L[kk] += map[static_cast<int64_t>(y) * g.W + x];
+            }
+        }
+    } else {
+        // Bilinear weights turn a projection error du into an error
+        // du * (l10 - l00) of the sample, and FP32 cannot place u closer than
+        // ~3e-5 px at u ~ 640. The projection is therefore evaluated in FP64
+        // (full rate on CDNA4, like unpacked FP32), from the FP64 voxel centre.
+        const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (i + 0.5);
+        const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (j + 0.5);
+        for (int v = 0; v < a.n; ++v) {
+            const ViewGeom &g = a.view[v];
+            const float *map = a.lmap + g.map_off;
+            const double ax = fma(static_cast<double>(g.P[0]), Xd, fma(static_cast<double>(g.P[1]), Yd, static_cast<double>(g.P[3])));
+            const double bx = fma(static_cast<double>(g.P[4]), Xd, fma(static_cast<double>(g.P[5]), Yd, static_cast<double>(g.P[7])));
+            const double cx = fma(static_cast<double>(g.P[8]), Xd, fma(static_cast<double>(g.P[9]), Yd, static_cast<double>(g.P[11])));
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (k0 + kk + 0.5);
+                const double c = fma(static_cast<double>(g.P[10]), Zd, cx);
+                if (!(c > 0.0)) continue;
+                const double r = 1.0 / c;
+                const double u = fma(static_cast<double>(g.P[2]), Zd, ax) * r;
+                const double w = fma(static_cast<double>(g.P[6]), Zd, bx) * r;
+                const double x0 = floor(u), y0 = floor(w);
+                const float fx = static_cast<float>(u - x0), fy = static_cast<float>(w - y0);
+                L[kk] += bilinear_sample(map, g.W, g.H, x0, y0, fx, fy);
+            }
+        }
+    }
+
+    if (i >= a.nx || j >= a.ny) return;
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        const int k = k0 + kk;
+        if (k < a.nz) {
+            const int64_t idx = (static_cast<int64_t>(k) * a.ny + j) * a.nx + i;
+            const float p = 1.0f / (1.0f + expf(-L[kk]));
+            a.post[idx] = p;
+            if (a.occ) a.occ[idx] = p > a.tau ? 1 : 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        occ[i] = post[i] > tau ? 1 : 0;
+}
+
+constexpr TileCfg kTiles[] = {
+    {32, 8, 4}, {32, 8, 2}, {32, 8, 8}, {16, 16, 4}, {64, 4, 4}, {64, 4, 2},
+};
+
+template <int S>
+hipError_t launch_fuse_s(const FuseArgs &a, int tile, hipStream_t s)
+{
+    const TileCfg &c = kTiles[tile];
+    const int64_t nb = static_cast<int64_t>((a.nx + c.tx - 1) / c.tx) * ((a.ny + c.ty - 1) / c.ty) *
+                       ((a.nz + c.kz - 1) / c.kz);
+    const dim3 grid(static_cast<unsigned>(nb)), block(c.tx * c.ty);
+    switch (tile) {
+    case 0: hipLaunchKernelGGL((fuse_kernel<32, 8, 4, S>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((fuse_kernel<32, 8, 2, S>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((fuse_kernel<32, 8, 8, S>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((fuse_kernel<16, 16, 4, S>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((fuse_kernel<64, 4, 4, S>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((fuse_kernel<64, 4, 2, S>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int tile_count() { return static_cast<int>(sizeof(kTiles) / sizeof(kTiles[0])); }
+const TileCfg &tile_cfg(int tile) { return kTiles[tile]; }
+int default_tile() { return 0; }
+
+hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s)
+{
+    const int64_t quads = (max_npix + 3) / 4;
+    const dim3 grid(static_cast<unsigned>((quads + 255) / 256), static_cast<unsigned>(a.n));
+    hipLaunchKernelGGL(slm_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s)
+{
+    return sampling == PSFS_BILINEAR ? launch_fuse_s<PSFS_BILINEAR>(a, tile, s)
+                                     : launch_fuse_s<PSFS_NEAREST>(a, tile, s);
+}
+
+hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(threshold_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, post, n, tau, occ);
+    return hipGetLastError();
+}
+
+}  // namespace psfs

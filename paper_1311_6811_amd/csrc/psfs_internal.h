@@ -1,0 +1,65 @@
+// Internal declarations shared by the host API and the kernels of libpsfs.
+// Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "psfs.h"
+
+namespace psfs {
+
+constexpr int kMaxViews = PSFS_MAX_VIEWS;
+constexpr int kMapAlignFloats = 64;     // per-view likelihood-map offset alignment
+constexpr int kNumXcd = 8;              // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// One view's inputs to the likelihood-map kernel (Eq. 1-2).
+struct SlmView {
+    const uint8_t *img;                 // [npix][3] u8
+    const float *mean;                  // [npix][3]
+    const float *var;                   // [npix][3]
+    int64_t npix;
+    int64_t map_off;                    // float offset of this view's map
+};
+
+struct SlmArgs {
+    SlmView view[kMaxViews];
+    float *lmap;
+    float k0;                           // -1.5*log(2*pi) - log_u
+    int32_t n;
+};
+
+// One view as the fusion kernels see it (Eq. 3-9). For nearest sampling the
+// host adds half of row 2 to rows 0 and 1, so floor(row0.X / row2.X) is the
+// nearest pixel floor(u + 1/2).
+struct ViewGeom {
+    float P[12];
+    int32_t W, H;
+    int64_t map_off;
+};
+
+struct FuseArgs {
+    ViewGeom view[kMaxViews];
+    const float *lmap;
+    float *post;
+    uint8_t *occ;                       // nullable
+    int32_t n, nx, ny, nz;
+    float ox, oy, oz, h;                // grid origin (corner) and voxel edge
+    float L0;                           // logit(prior)
+    float tau;                          // threshold on the posterior
+};
+
+struct TileCfg {
+    int tx, ty, kz;                     // x-by-y lanes per workgroup, z voxels per lane
+};
+
+int tile_count();
+const TileCfg &tile_cfg(int tile);
+int default_tile();
+
+hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s);
+hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s);
+hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
+
+}  // namespace psfs

@@ -1,0 +1,175 @@
+"""The C-ABI library loads, exports every symbol psfs.h declares, and rejects
+bad arguments before touching any device. No GPU needed (no compute call here
+reaches a kernel launch)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1311_6811_amd as psfs
+from paper_1311_6811_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psfs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(psfs_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each
+    assert set(names) <= set(L.SIGNATURES), set(names) - set(L.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (psfs_\w+)", out))
+    assert set(names) == exported, (set(names) ^ exported)
+
+
+def test_header_compiles_as_c_and_validates(tmp_path, lib):
+    exe = str(tmp_path / "abi_check")
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "abi_check.c"), "-o", exe,
+                           L.LIB_PATH, f"-Wl,-rpath,{os.path.dirname(L.LIB_PATH)}"])
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    sizes = re.search(r"sizes (\d+) (\d+) (\d+)", out.stdout).groups()
+    assert tuple(map(int, sizes)) == (C.sizeof(L.psfs_camera), C.sizeof(L.psfs_grid), C.sizeof(L.psfs_params))
+
+
+def _plan(lib):
+    h = C.c_void_p()
+    assert lib.psfs_plan_create(C.byref(h)) == 0
+    return h
+
+
+def _cam(W=8, H=6):
+    P = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1]], np.float32)
+    return psfs.make_camera(W, H, P)
+
+
+def test_status_strings(lib):
+    for s in range(-7, 1):
+        assert lib.psfs_status_str(s)
+    assert lib.psfs_version() == 1
+
+
+def test_default_params(lib):
+    p = L.psfs_params()
+    lib.psfs_default_params(C.byref(p))
+    assert p.prior == 0.5 and p.threshold == 0.5 and p.sampling == 0
+    assert p.log_u == pytest.approx(-3 * np.log(256.0), rel=1e-7)
+
+
+def test_camera_validation(lib):
+    h = _plan(lib)
+    cams = (L.psfs_camera * 17)(*([_cam()] * 17))
+    assert lib.psfs_set_cameras(h, 17, cams) == -2
+    assert lib.psfs_set_cameras(h, -1, cams) == -2
+    assert lib.psfs_set_cameras(h, 2, None) == -1
+    bad = _cam(0, 5)
+    assert lib.psfs_set_cameras(h, 1, (L.psfs_camera * 1)(bad)) == -2
+    nan = _cam()
+    nan.P[3] = float("nan")
+    assert lib.psfs_set_cameras(h, 1, (L.psfs_camera * 1)(nan)) == -2
+    assert b"not finite" in lib.psfs_last_error()
+    huge = _cam(65535, 65535)
+    assert lib.psfs_set_cameras(h, 1, (L.psfs_camera * 1)(huge)) == -2
+    assert lib.psfs_set_cameras(h, 0, None) == 0          # zero views is valid
+    assert lib.psfs_set_cameras(None, 0, None) == -1
+    lib.psfs_plan_destroy(h)
+
+
+def test_grid_and_params_validation(lib):
+    h = _plan(lib)
+    g = psfs.make_grid(-1, 2, 2, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == -2
+    g = psfs.make_grid(2048, 2048, 512, (0, 0, 0), 0.1)       # 2^31 voxels
+    assert lib.psfs_set_grid(h, C.byref(g)) == -2
+    g = psfs.make_grid(2, 2, 2, (0, 0, 0), 0.0)
+    assert lib.psfs_set_grid(h, C.byref(g)) == -2
+    g = psfs.make_grid(0, 3, 3, (0, 0, 0), 0.1)                # empty grid is valid
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    for prior, log_u, tau, samp, want in ((0.0, -1, 0.5, 0, -2), (1.0, -1, 0.5, 0, -2), (0.5, float("inf"), 0.5, 0, -2),
+                                          (0.5, -1, 1.5, 0, -2), (0.5, -1, 0.5, 2, -1), (0.3, -1, 0.0, 1, 0)):
+        p = L.psfs_params(prior, log_u, tau, samp)
+        assert lib.psfs_set_params(h, C.byref(p)) == want
+    lib.psfs_plan_destroy(h)
+
+
+def test_not_ready_and_pointer_checks(lib):
+    h = _plan(lib)
+    fake = C.c_void_p(0x100000)
+    assert lib.psfs_set_background(h, 0, fake, fake) == -3          # cameras not set
+    assert lib.psfs_lmap_floats(h) == -3
+    assert lib.psfs_workspace_bytes(h) == 0
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_lmap_floats(h) == 128
+    assert lib.psfs_lmap_offset(h, 1) == 64
+    assert lib.psfs_lmap_offset(h, 2) == -2
+    assert lib.psfs_workspace_bytes(h) == 512
+    assert lib.psfs_set_background(h, 2, fake, fake) == -2
+    assert lib.psfs_set_background(h, 0, None, fake) == -1
+    assert lib.psfs_set_background(h, 0, C.c_void_p(0x100004), fake) == -1   # misaligned
+    imgs = L.ptr_array([0x100000, 0x100000])
+    assert lib.psfs_likelihood(h, imgs, fake, None) == -3            # backgrounds missing
+    assert lib.psfs_set_background(h, 0, fake, fake) == 0
+    assert lib.psfs_set_background(h, 1, fake, fake) == 0
+    assert lib.psfs_likelihood(h, L.ptr_array([0x100000, 0x100001]), fake, None) == -1  # image misaligned
+    assert lib.psfs_likelihood(h, None, fake, None) == -1
+    assert lib.psfs_fuse(h, fake, fake, None, None) == -3            # grid missing
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert lib.psfs_fuse(h, fake, None, None, None) == -1
+    assert lib.psfs_fuse(h, fake, C.c_void_p(0x100008), None, None) == -1
+    assert lib.psfs_reconstruct(h, imgs, fake, None, fake, 100, None) == -4   # workspace too small
+    assert lib.psfs_reconstruct(h, imgs, fake, None, None, 4096, None) == -4
+    # setting cameras again forgets the backgrounds
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_reconstruct(h, imgs, fake, None, fake, 4096, None) == -3
+    lib.psfs_plan_destroy(h)
+
+
+def test_empty_work_is_a_no_op_without_device(lib):
+    h = _plan(lib)
+    assert lib.psfs_set_cameras(h, 0, None) == 0
+    g = psfs.make_grid(0, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert lib.psfs_reconstruct(h, None, None, None, None, 0, None) == 0
+    assert lib.psfs_threshold(None, 0, 0.5, None, None) == 0
+    assert lib.psfs_threshold(None, -1, 0.5, None, None) == -2
+    assert lib.psfs_threshold(None, 5, 1.5, None, None) == -2
+    lib.psfs_plan_destroy(h)
+
+
+def test_tiles(lib):
+    tiles = psfs.tiles()
+    assert len(tiles) >= 4
+    for tx, ty, kz in tiles:
+        assert tx * ty in (64, 128, 256, 512, 1024) and tx * ty % 64 == 0 and kz >= 1
+    assert lib.psfs_tile_describe(len(tiles), None, None, None) == -2
+    h = _plan(lib)
+    assert lib.psfs_set_tile(h, len(tiles)) == -2
+    assert lib.psfs_set_tile(h, -1) == 0
+    lib.psfs_plan_destroy(h)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L.lib()

@@ -1,0 +1,183 @@
+"""GPU forward path (likelihood maps, fusion, threshold) against the FP64 oracle.
+
+Posterior: within 1e-5 absolute; where a voxel's projection lies within 1e-3 px
+of a pixel-rounding boundary in some view, any admissible pixel choice is
+correct, so the GPU value must match one of them. Occupancy: bit-exact where
+the oracle's posterior is more than 1e-4 from the threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1311_6811_amd as psfs
+from oracle import oracle as O
+from synth import scene as S
+from tests.gpu_util import (assert_occupancy_parity, assert_posterior_parity, plan_for, upload)
+
+pytestmark = pytest.mark.gpu
+
+LMAP_RTOL, LMAP_ATOL = 2e-6, 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_forward(frame, **kw):
+    ims, mus, vs = upload(frame)
+    plan = plan_for(frame, mus, vs, **kw)
+    lmap = plan.likelihood(ims)
+    post, occ = plan.fuse(lmap)
+    post2, occ2 = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    assert torch.equal(post, post2) and torch.equal(occ, occ2)
+    return plan, lmap, post, occ
+
+
+def check_lmaps(plan, lmap, frame, log_u=O.LOG_U_DEFAULT):
+    worst = 0.0
+    for k in range(frame.n):
+        want = O.log2slm(frame.images[k], frame.mean[k], frame.var[k], log_u)
+        got = plan.lmap_view(lmap, k).cpu().numpy().astype(np.float64)
+        err = np.abs(got - want) - LMAP_RTOL * np.abs(want)
+        assert err.max() <= LMAP_ATOL, f"view {k}: lmap error {err.max():.3e}"
+        worst = max(worst, float(np.abs(got - want).max()))
+    return worst
+
+
+def oracle_forward(frame, prior=0.5, log_u=O.LOG_U_DEFAULT):
+    maps = [O.slm(i, m, v, log_u) for i, m, v in zip(frame.images, frame.mean, frame.var)]
+    ref = O.posterior(frame.cams, frame.grid, maps, prior)
+    combos = lambda v: O.voxel_combos(frame.cams, frame.grid, maps, v, prior)  # noqa: E731
+    return ref, combos
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_forward_parity_named_workloads(cfg):
+    say(f"forward parity config {cfg}")
+    fr = S.config_frame(cfg, 0)
+    plan, lmap, post, occ = run_forward(fr)
+    check_lmaps(plan, lmap, fr)
+    ref, combos = oracle_forward(fr)
+    worst = assert_posterior_parity(post, ref, combos=combos)
+    assert_occupancy_parity(occ, ref)
+    say(f"  max posterior error {worst:.2e}, ambiguous {ref.ambiguous.mean():.4f}")
+
+
+def test_forward_parity_large_grid_12_views():
+    say("forward parity 256^3 x 12 views 1280x720")
+    fr = S.config_frame(2, 5)
+    plan, lmap, post, occ = run_forward(fr)
+    check_lmaps(plan, lmap, fr)
+    ref, combos = oracle_forward(fr)
+    assert_posterior_parity(post, ref, combos=combos, n_enum=100)
+    assert_occupancy_parity(occ, ref)
+
+
+def test_ragged_grid_odd_images_mixed_sizes():
+    say("ragged grid 37x29x23, odd image sizes")
+    rng = np.random.default_rng(5)
+    cams = [S.look_at_camera((4 * np.cos(t), 4 * np.sin(t), 1.2), f, W, H)
+            for t, (f, W, H) in zip((0.3, 1.9, 3.7, 5.1), ((300, 321, 241), (250, 160, 117), (400, 401, 303), (90, 97, 61)))]
+    grid = S.Grid(37, 29, 23, np.array([-0.9, -0.8, -1.05], np.float32), np.float32(0.047))
+    body = S.make_body(rng)
+    fr = S.render_frame(10, 0, cams, grid, body, (10, 0))
+    plan, lmap, post, occ = run_forward(fr, prior=0.35, threshold=0.6)
+    check_lmaps(plan, lmap, fr)
+    ref, combos = oracle_forward(fr, prior=0.35)
+    assert_posterior_parity(post, ref, combos=combos)
+    assert_occupancy_parity(occ, ref, tau=0.6)
+
+
+@pytest.mark.parametrize("n", [1, 16])
+def test_view_count_extremes(n):
+    say(f"view count {n}")
+    f, W, H = S.IMAGE_CLASSES[0]
+    cams = S.ring_rig(n, f, W, H, phase=0.1)
+    grid = S.cube_grid(40, 2.0)
+    body = S.make_body(np.random.default_rng(n))
+    fr = S.render_frame(11, n, cams, grid, body, (11, n))
+    plan, lmap, post, occ = run_forward(fr)
+    ref, combos = oracle_forward(fr)
+    assert_posterior_parity(post, ref, combos=combos)
+    assert_occupancy_parity(occ, ref)
+
+
+def test_zero_views_gives_prior_and_empty_grid_is_noop():
+    grid = S.cube_grid(17, 2.0)
+    plan = psfs.Plan([], grid, prior=0.3, threshold=0.25)
+    post, occ = plan.reconstruct([])
+    torch.cuda.synchronize()
+    assert float((post - 0.3).abs().max()) < 1e-6
+    assert bool(torch.all(occ == 1))
+    empty = S.Grid(0, 5, 5, np.zeros(3, np.float32), np.float32(0.1))
+    plan = psfs.Plan([], empty)
+    post, occ = plan.reconstruct([])
+    torch.cuda.synchronize()
+    assert post.numel() == 0
+
+
+def test_camera_inside_grid_voxels_behind():
+    say("camera inside the grid")
+    cam = S.look_at_camera((0.05, 0.02, 0.01), f=150.0, W=160, H=120, target=(3.0, 0.3, 0.2))
+    grid = S.cube_grid(48, 2.0)
+    body = S.make_body(np.random.default_rng(3), shift=(0.6, 0.0, 0.0))
+    fr = S.render_frame(12, 0, [cam] + S.ring_rig(3, 300, 320, 240), grid, body, (12, 0))
+    plan, lmap, post, occ = run_forward(fr)
+    ref, combos = oracle_forward(fr)
+    assert_posterior_parity(post, ref, combos=combos)
+    assert_occupancy_parity(occ, ref)
+
+
+def test_every_tile_gives_identical_bits():
+    fr = S.config_frame(1, 0)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    lmap = plan.likelihood(ims)
+    outs = []
+    for t in range(len(psfs.tiles())):
+        plan.set_tile(t)
+        post, occ = plan.fuse(lmap)
+        outs.append((post, occ))
+    torch.cuda.synchronize()
+    for post, occ in outs[1:]:
+        assert torch.equal(post, outs[0][0]) and torch.equal(occ, outs[0][1])
+
+
+def test_bilinear_posterior_parity():
+    say("bilinear posterior")
+    fr = S.config_frame(0, 2)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs, sampling=psfs.BILINEAR)
+    post, occ = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    l2s = [O.log2slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
+    L = O.bilinear_logits(fr.cams, fr.grid, l2s)
+    want = 1.0 / (1.0 + np.exp(-L))
+    err = np.abs(post.cpu().numpy().astype(np.float64) - want)
+    assert err.max() <= 1e-5, err.max()
+    decided = np.abs(want - 0.5) > 1e-4
+    assert np.array_equal(occ.cpu().numpy()[decided], (want > 0.5).astype(np.uint8)[decided])
+
+
+def test_all_background_views_give_empty_grid():
+    fr = S.config_frame(0, 4)
+    rng = np.random.default_rng(8)
+    fr.images = [rng.integers(0, 256, (c.height, c.width, 3)).astype(np.uint8) for c in fr.cams]
+    fr.mean = [im.astype(np.float32) for im in fr.images]
+    plan, lmap, post, occ = run_forward(fr)
+    assert int(occ.sum()) == 0
+    assert float(post.max()) <= 0.5
+
+
+def test_threshold_entry_point():
+    torch.manual_seed(0)
+    post = torch.rand(1000003, device="cuda")
+    post[:5] = torch.tensor([0.0, 0.25, 0.5, 0.75, 1.0], device="cuda")
+    for tau in (0.0, 0.25, 0.5, 1.0):
+        occ = psfs.threshold(post, tau)
+        torch.cuda.synchronize()
+        assert torch.equal(occ, (post > tau).to(torch.uint8))
