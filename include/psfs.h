@@ -150,6 +150,33 @@ int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *p
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,
                    void *stream);
 
+/* ---------------------------------------- differentiable variant (bilinear) */
+
+/* Workspace of psfs_diff_forward / psfs_diff_backward: likelihood maps,
+ * adjoint maps and reduction partials. 0 if cameras or grid unset. */
+size_t psfs_diff_workspace_bytes(const psfs_plan *plan);
+
+/* Logits L = logit(prior) + sum_k l~_k with l~_k the bilinear sample of view
+ * k's log(2*SLM) (PSFS_BILINEAR rule, whatever params.sampling says), FP32
+ * [nz][ny][nx]; and the mean binary cross-entropy with logits against the u8
+ * 0/1 labels over the region sub = {i0,i1,j0,j1,k0,k1} (half-open, host
+ * array; NULL = whole grid), written as one FP32 to loss_dev.
+ * The workspace keeps the likelihood maps for psfs_diff_backward. */
+int psfs_diff_forward(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *labels_dev,
+                      const int32_t *sub, float *logits_dev, float *loss_dev,
+                      void *workspace_dev, size_t workspace_bytes, void *stream);
+
+/* Gradient of grad_loss * loss with respect to every view's background mean
+ * and variance (FP32 [H][W][3] each; host arrays of n device pointers) and
+ * camera matrices (FP32 [n][12], row-major). grad_loss_dev points to one FP32
+ * on the device. Requires the workspace exactly as psfs_diff_forward left it
+ * for the same plan, images, labels and sub; projections are recomputed, not
+ * stored. Every output element is overwritten. */
+int psfs_diff_backward(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *labels_dev,
+                       const int32_t *sub, const float *logits_dev, const float *grad_loss_dev,
+                       float *const *gmean_dev, float *const *gvar_dev, float *gP_dev,
+                       void *workspace_dev, size_t workspace_bytes, void *stream);
+
 /* Kernel variant selection used by the batch and forward paths:
  * tile = index into the library's fusion tile table (see psfs_tile_count),
  * or -1 for the tuned/default choice. */

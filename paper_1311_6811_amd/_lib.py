@@ -64,6 +64,10 @@ SIGNATURES = {
     "psfs_fuse": (C.c_int, [vp, vp, vp, vp, vp]),
     "psfs_reconstruct": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
     "psfs_threshold": (C.c_int, [vp, C.c_int64, C.c_float, vp, vp]),
+    "psfs_diff_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_diff_forward": (C.c_int, [vp, C.POINTER(vp), vp, i32p, vp, vp, vp, C.c_size_t, vp]),
+    "psfs_diff_backward": (C.c_int, [vp, C.POINTER(vp), vp, i32p, vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp,
+                                     C.c_size_t, vp]),
     "psfs_tile_count": (C.c_int, []),
     "psfs_tile_describe": (C.c_int, [C.c_int, i32p, i32p, i32p]),
     "psfs_set_tile": (C.c_int, [vp, C.c_int]),

@@ -187,6 +187,57 @@ class Plan:
                                          ws.numel(), _stream()))
         return post, occ
 
+    # ------------------------------------------- differentiable variant
+    def diff_workspace_bytes(self) -> int:
+        return int(L.lib().psfs_diff_workspace_bytes(self._h))
+
+    def new_diff_workspace(self) -> torch.Tensor:
+        n = max(self.diff_workspace_bytes(), 256)
+        return torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def _sub(sub):
+        if sub is None:
+            return None
+        arr = (C.c_int32 * 6)(*[int(x) for x in sub])
+        return arr
+
+    def diff_forward(self, images, labels: torch.Tensor, sub=None, logits=None, loss=None, workspace=None):
+        """Bilinear logits [nz][ny][nx] and mean BCE loss over `sub` (default:
+        whole grid). Returns (logits, loss, workspace); keep the workspace
+        untouched for diff_backward."""
+        g = self.grid
+        shape = (g.nz, g.ny, g.nx)
+        ims = self._images(images)
+        lab = _dev(labels, torch.uint8, "labels", shape)
+        logits = logits if logits is not None else torch.empty(shape, dtype=torch.float32, device="cuda")
+        loss = loss if loss is not None else torch.empty((), dtype=torch.float32, device="cuda")
+        ws = workspace if workspace is not None else self.new_diff_workspace()
+        L.check(L.lib().psfs_diff_forward(self._h, ims, lab, self._sub(sub), _dev(logits, torch.float32, "logits", shape),
+                                          _dev(loss, torch.float32, "loss"), _dev(ws, torch.uint8, "workspace"),
+                                          ws.numel(), _stream()))
+        return logits, loss, ws
+
+    def diff_backward(self, images, labels, logits, grad_loss: torch.Tensor, workspace, sub=None,
+                      gmeans=None, gvars=None, gP=None):
+        """Gradients of grad_loss * loss w.r.t. background means, variances
+        (lists of [H][W][3]) and camera matrices ([n][3][4])."""
+        g = self.grid
+        shape = (g.nz, g.ny, g.nx)
+        ims = self._images(images)
+        gl = grad_loss.detach().to(device="cuda", dtype=torch.float32).contiguous().reshape(())
+        gmeans = gmeans if gmeans is not None else [torch.empty((c.height, c.width, 3), dtype=torch.float32, device="cuda") for c in self.cams]
+        gvars = gvars if gvars is not None else [torch.empty((c.height, c.width, 3), dtype=torch.float32, device="cuda") for c in self.cams]
+        gP = gP if gP is not None else torch.empty((max(self.n, 1), 3, 4), dtype=torch.float32, device="cuda")
+        gm_ptr = L.ptr_array([_dev(t, torch.float32, f"gmean[{k}]", (c.height, c.width, 3)) for k, (t, c) in enumerate(zip(gmeans, self.cams))])
+        gv_ptr = L.ptr_array([_dev(t, torch.float32, f"gvar[{k}]", (c.height, c.width, 3)) for k, (t, c) in enumerate(zip(gvars, self.cams))])
+        L.check(L.lib().psfs_diff_backward(self._h, ims, _dev(labels, torch.uint8, "labels", shape), self._sub(sub),
+                                           _dev(logits, torch.float32, "logits", shape), gl.data_ptr(), gm_ptr, gv_ptr,
+                                           _dev(gP, torch.float32, "gP"), _dev(workspace, torch.uint8, "workspace"),
+                                           workspace.numel(), _stream()))
+        self._keep["grad_loss"] = gl
+        return gmeans, gvars, gP[: self.n]
+
 
 def tiles():
     n = L.lib().psfs_tile_count()

@@ -196,6 +196,71 @@ int enqueue_fuse(const psfs_plan *p, const float *lmap, float *post, uint8_t *oc
     return PSFS_OK;
 }
 
+
+// Workspace of the differentiable pass: likelihood maps, adjoint maps, loss
+// partials, camera-gradient partials; each region 256-byte aligned.
+struct DiffLayout {
+    size_t lmap, adj, loss, cam, total;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+DiffLayout diff_layout(const psfs_plan *p)
+{
+    DiffLayout L{};
+    const size_t maps = static_cast<size_t>(map_floats(p)) * sizeof(float);
+    const int64_t nbf = p->has_grid ? diff_fwd_blocks(p->grid.nx, p->grid.ny, p->grid.nz) : 0;
+    const int64_t nbb = p->has_grid ? diff_bwd_blocks(p->grid.nx, p->grid.ny, p->grid.nz) : 0;
+    L.lmap = 0;
+    L.adj = align256(maps);
+    L.loss = L.adj + align256(maps);
+    L.cam = L.loss + align256(static_cast<size_t>(nbf) * sizeof(double));
+    L.total = L.cam + align256(static_cast<size_t>(nbb) * 12 * (p->n > 0 ? p->n : 0) * sizeof(float));
+    return L;
+}
+
+int check_region(const psfs_plan *p, const int32_t *sub, int32_t out[6], float *inv_count)
+{
+    const int32_t dims[3] = {p->grid.nx, p->grid.ny, p->grid.nz};
+    for (int d = 0; d < 3; ++d) {
+        const int32_t lo = sub ? sub[2 * d] : 0, hi = sub ? sub[2 * d + 1] : dims[d];
+        if (lo < 0 || hi < lo || hi > dims[d]) return fail(PSFS_E_RANGE, "loss region axis %d [%d,%d) outside [0,%d)", d, lo, hi, dims[d]);
+        out[2 * d] = lo;
+        out[2 * d + 1] = hi;
+    }
+    const int64_t cnt = static_cast<int64_t>(out[1] - out[0]) * (out[3] - out[2]) * (out[5] - out[4]);
+    *inv_count = cnt > 0 ? static_cast<float>(1.0 / static_cast<double>(cnt)) : 0.0f;
+    return PSFS_OK;
+}
+
+int prepare_diff(const psfs_plan *p, const uint8_t *const *images, const uint8_t *labels, const int32_t *sub,
+                 void *ws, size_t ws_bytes, DiffArgs &a, DiffLayout &L)
+{
+    int rc = need_backgrounds(p);
+    if (rc) return rc;
+    if ((rc = need_grid(p))) return rc;
+    if ((rc = check_images(p, images))) return rc;
+    if (nvox(p->grid) > 0 && !labels) return fail(PSFS_E_ARG, "labels is NULL");
+    a = DiffArgs{};
+    if ((rc = check_region(p, sub, a.sub, &a.inv_count))) return rc;
+    L = diff_layout(p);
+    if (!ws || ws_bytes < L.total || !aligned(ws, 256))
+        return fail(PSFS_E_WORKSPACE, "differentiable workspace needs %zu bytes, 256-byte aligned (got %zu)", L.total, ws_bytes);
+    FuseArgs f{};
+    fill_geometry(p, PSFS_BILINEAR, f);
+    for (int k = 0; k < p->n; ++k) a.view[k] = f.view[k];
+    char *base = static_cast<char *>(ws);
+    a.lmap = reinterpret_cast<const float *>(base + L.lmap);
+    a.adj = reinterpret_cast<float *>(base + L.adj);
+    a.loss_part = reinterpret_cast<double *>(base + L.loss);
+    a.cam_part = reinterpret_cast<float *>(base + L.cam);
+    a.labels = labels;
+    a.n = p->n;
+    a.nx = p->grid.nx; a.ny = p->grid.ny; a.nz = p->grid.nz;
+    a.ox = f.ox; a.oy = f.oy; a.oz = f.oz; a.h = f.h;
+    a.L0 = f.L0;
+    return PSFS_OK;
+}
 }  // namespace
 }  // namespace psfs
 
@@ -381,6 +446,71 @@ int psfs_threshold(const float *posterior_dev, int64_t nvox_, float tau, uint8_t
     if (rc) return rc;
     hipError_t e = launch_threshold(posterior_dev, nvox_, tau, occ_dev, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "threshold kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
+size_t psfs_diff_workspace_bytes(const psfs_plan *plan)
+{
+    if (!plan || plan->n < 0 || !plan->has_grid) return 0;
+    return diff_layout(plan).total;
+}
+
+int psfs_diff_forward(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *labels_dev,
+                      const int32_t *sub, float *logits_dev, float *loss_dev, void *workspace_dev,
+                      size_t workspace_bytes, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    DiffArgs a;
+    DiffLayout L;
+    int rc = prepare_diff(plan, images_dev, labels_dev, sub, workspace_dev, workspace_bytes, a, L);
+    if (rc) return rc;
+    if (!loss_dev) return fail(PSFS_E_ARG, "loss is NULL");
+    if (nvox(plan->grid) > 0 && (!logits_dev || !aligned(logits_dev, 16))) return fail(PSFS_E_ARG, "logits must be a 16-byte aligned device pointer");
+    if ((rc = check_device())) return rc;
+    a.logits = logits_dev;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = enqueue_likelihood(plan, images_dev, const_cast<float *>(a.lmap), s))) return rc;
+    hipError_t e = launch_diff_forward(a, loss_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "differentiable forward launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
+int psfs_diff_backward(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *labels_dev,
+                       const int32_t *sub, const float *logits_dev, const float *grad_loss_dev,
+                       float *const *gmean_dev, float *const *gvar_dev, float *gP_dev, void *workspace_dev,
+                       size_t workspace_bytes, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    DiffArgs a;
+    DiffLayout L;
+    int rc = prepare_diff(plan, images_dev, labels_dev, sub, workspace_dev, workspace_bytes, a, L);
+    if (rc) return rc;
+    if (!grad_loss_dev) return fail(PSFS_E_ARG, "grad_loss is NULL");
+    if (nvox(plan->grid) > 0 && !logits_dev) return fail(PSFS_E_ARG, "logits is NULL");
+    if (plan->n > 0) {
+        if (!gmean_dev || !gvar_dev || !gP_dev) return fail(PSFS_E_ARG, "gradient output array is NULL");
+        if (!aligned(gP_dev, 4)) return fail(PSFS_E_ARG, "gP must be 4-byte aligned");
+        for (int k = 0; k < plan->n; ++k)
+            if (!gmean_dev[k] || !gvar_dev[k] || !aligned(gmean_dev[k], 16) || !aligned(gvar_dev[k], 16))
+                return fail(PSFS_E_ARG, "gradient outputs of view %d must be 16-byte aligned device pointers", k);
+    }
+    if ((rc = check_device())) return rc;
+    a.logits = const_cast<float *>(logits_dev);
+    a.grad_loss = grad_loss_dev;
+    ChainArgs c{};
+    c.n = plan->n;
+    c.adj = a.adj;
+    c.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(plan->params.log_u));
+    int64_t max_np = 0;
+    for (int k = 0; k < plan->n; ++k) {
+        const int64_t np = static_cast<int64_t>(plan->cams[k].width) * plan->cams[k].height;
+        c.view[k] = ChainView{images_dev[k], plan->mean[k], plan->var[k], gmean_dev[k], gvar_dev[k], np, map_offset(plan, k)};
+        if (np > max_np) max_np = np;
+    }
+    hipError_t e = launch_diff_backward(a, c, map_floats(plan), max_np, gP_dev, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "differentiable backward launch");
     return PSFS_OK;
     PSFS_GUARD_END
 }

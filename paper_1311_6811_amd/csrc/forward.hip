@@ -8,33 +8,13 @@
 // gives P(S_k|V=1) = SLM_k and P(S_k|V=0) = 1/2, so each view that sees a voxel
 // adds log(2*SLM_k) to the logit of Eq. 3. With SLM = u/(u+N) (Eq. 1-2, equal
 // pixel priors), log(2*SLM) = log 2 - softplus(log N - log u).
-#include "psfs_internal.h"
+#include "kernels_common.h"
 
 namespace psfs {
 
 namespace {
 
-constexpr float kLn2 = 0.693147180559945309f;
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// log(2*SLM) of one pixel. k0 = -1.5*log(2*pi) - log_u, so that
-// log N - log u = k0 - 1/2 * (sum_c d_c^2/v_c + log(v0*v1*v2)).
-__device__ __forceinline__ float log2slm(float i0, float i1, float i2, float m0, float m1, float m2,
-                                         float v0, float v1, float v2, float k0)
-{
-    const float d0 = i0 - m0, d1 = i1 - m1, d2 = i2 - m2;
-    const float q = d0 * d0 / v0 + d1 * d1 / v1 + d2 * d2 / v2;
-    const float half_logdet = 0.5f * (logf(v0 * v1) + logf(v2));
-    const float d = (k0 - half_logdet) - 0.5f * q;
-    const float softplus = fmaxf(d, 0.0f) + log1pf(expf(-fabsf(d)));
-    return kLn2 - softplus;
-}
-
-__device__ __forceinline__ float byte_of(uint32_t w, int b)
-{
-    return static_cast<float>((w >> (8 * b)) & 0xffu);
-}
+using namespace dev;
 
 // One lane converts 4 consecutive pixels: 12 image bytes (3 dwords) and 12
 // floats each of mean and variance (3 x 16 B), all naturally aligned.
@@ -70,33 +50,6 @@ __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
             out[p - p0] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], a.k0);
         }
     }
-}
-
-// Bilinear sample of a likelihood map at (x0 + fx, y0 + fy); taps outside the
-// image count 0. x0, y0 are integral doubles (possibly far outside the image).
-__device__ __forceinline__ float bilinear_sample(const float *map, int W, int H, double x0, double y0, float fx, float fy)
-{
-    if (!(x0 >= -1.0 && x0 < W && y0 >= -1.0 && y0 < H)) return 0.0f;
-    const int ix = static_cast<int>(x0), iy = static_cast<int>(y0);
-    const bool xin0 = ix >= 0, xin1 = ix + 1 < W, yin0 = iy >= 0, yin1 = iy + 1 < H;
-    const int64_t base = static_cast<int64_t>(iy) * W + ix;
-    const float l00 = (xin0 && yin0) ? map[base] : 0.0f;
-    const float l10 = (xin1 && yin0) ? map[base + 1] : 0.0f;
-    const float l01 = (xin0 && yin1) ? map[base + W] : 0.0f;
-    const float l11 = (xin1 && yin1) ? map[base + W + 1] : 0.0f;
-    const float top = fmaf(fx, l10 - l00, l00);
-    const float bot = fmaf(fx, l11 - l01, l01);
-    return fmaf(fy, bot - top, top);
-}
-
-// Workgroups are dispatched round-robin over the XCDs; give each XCD one
-// contiguous range of logical blocks (z-slabs of the grid), so that its L2
-// holds one band of rows of every likelihood map.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb)
-{
-    const int64_t per = nb / kNumXcd;
-    if (bid >= per * kNumXcd) return bid;
-    return (bid % kNumXcd) * per + bid / kNumXcd;
 }
 
 // Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,

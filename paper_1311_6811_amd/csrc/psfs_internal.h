@@ -50,6 +50,42 @@ struct FuseArgs {
     float tau;                          // threshold on the posterior
 };
 
+// Differentiable variant: bilinear logits, BCE loss and adjoint (one view
+// geometry per view with the raw camera matrix).
+struct DiffArgs {
+    ViewGeom view[kMaxViews];
+    const float *lmap;                  // log(2*SLM) maps
+    float *adj;                         // adjoint maps dLoss/dlog(2*SLM), same layout
+    const uint8_t *labels;              // [nz][ny][nx] 0/1
+    float *logits;                      // [nz][ny][nx]
+    const float *grad_loss;             // device scalar (backward)
+    double *loss_part;                  // one partial sum per forward workgroup
+    float *cam_part;                    // [backward workgroup][n][12] partial camera gradients
+    int32_t n, nx, ny, nz;
+    float ox, oy, oz, h;
+    float L0;                           // logit(prior)
+    float inv_count;                    // 1 / |loss region| (0 for an empty region)
+    int32_t sub[6];                     // loss region [i0,i1) x [j0,j1) x [k0,k1)
+};
+
+// Pixel chain: adjoint maps -> gradients of the background means/variances.
+struct ChainView {
+    const uint8_t *img;
+    const float *mean;
+    const float *var;
+    float *gmean;
+    float *gvar;
+    int64_t npix;
+    int64_t map_off;
+};
+
+struct ChainArgs {
+    ChainView view[kMaxViews];
+    const float *adj;
+    float k0;
+    int32_t n;
+};
+
 struct TileCfg {
     int tx, ty, kz;                     // x-by-y lanes per workgroup, z voxels per lane
 };
@@ -60,6 +96,11 @@ int default_tile();
 
 hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s);
 hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s);
+int64_t diff_fwd_blocks(int nx, int ny, int nz);
+int64_t diff_bwd_blocks(int nx, int ny, int nz);
+hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);
+hipError_t launch_diff_backward(const DiffArgs &a, const ChainArgs &c, int64_t map_floats, int64_t max_npix,
+                                float *gP, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 
 }  // namespace psfs

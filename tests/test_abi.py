@@ -173,3 +173,36 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.lib()
+
+
+def test_diff_validation_without_device(lib):
+    h = _plan(lib)
+    assert lib.psfs_diff_workspace_bytes(h) == 0
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    g = psfs.make_grid(40, 8, 9, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    fake = C.c_void_p(0x100000)
+    for k in range(2):
+        assert lib.psfs_set_background(h, k, fake, fake) == 0
+    need = lib.psfs_diff_workspace_bytes(h)
+    # two padded maps (2 x 128 floats), one FP64 partial per forward workgroup,
+    # 2 x 12 FP32 partials per backward workgroup, each region 256-byte aligned
+    nb = 2 * 1 * 3
+    want = 512 + 512 + 256 * ((nb * 8 + 255) // 256) + 256 * ((nb * 24 * 4 + 255) // 256)
+    assert need == want
+    imgs = L.ptr_array([0x100000, 0x100000])
+    ws = C.c_void_p(0x200000)
+    bad = (C.c_int32 * 6)(0, 41, 0, 8, 0, 9)
+    assert lib.psfs_diff_forward(h, imgs, fake, bad, fake, fake, ws, need, None) == -2
+    bad = (C.c_int32 * 6)(3, 2, 0, 8, 0, 9)
+    assert lib.psfs_diff_forward(h, imgs, fake, bad, fake, fake, ws, need, None) == -2
+    assert lib.psfs_diff_forward(h, imgs, fake, None, fake, fake, ws, need - 1, None) == -4
+    assert lib.psfs_diff_forward(h, imgs, fake, None, fake, fake, C.c_void_p(0x200010), need, None) == -4
+    assert lib.psfs_diff_forward(h, imgs, None, None, fake, fake, ws, need, None) == -1
+    assert lib.psfs_diff_forward(h, imgs, fake, None, fake, None, ws, need, None) == -1
+    assert lib.psfs_diff_backward(h, imgs, fake, None, fake, None, L.ptr_array([0x100000] * 2),
+                                  L.ptr_array([0x100000] * 2), fake, ws, need, None) == -1
+    assert lib.psfs_diff_backward(h, imgs, fake, None, fake, fake, L.ptr_array([0x100000, 0x100004]),
+                                  L.ptr_array([0x100000] * 2), fake, ws, need, None) == -1
+    lib.psfs_plan_destroy(h)
