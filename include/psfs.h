@@ -177,6 +177,66 @@ int psfs_diff_backward(psfs_plan *plan, const uint8_t *const *images_dev, const 
                        float *const *gmean_dev, float *const *gvar_dev, float *gP_dev,
                        void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------ batching */
+
+/* One frame of a batch: its own grid, views, images, background and outputs.
+ * Host arrays (cams, images_dev, mean_dev, var_dev) are copied at create /
+ * update; device pointers are borrowed. */
+typedef struct psfs_frame {
+    psfs_grid grid;
+    int32_t n;                          /* 1..PSFS_MAX_VIEWS */
+    const psfs_camera *cams;
+    const uint8_t *const *images_dev;
+    const float *const *mean_dev;
+    const float *const *var_dev;
+    float *posterior_dev;               /* [nz][ny][nx] */
+    uint8_t *occ_dev;                   /* nullable */
+} psfs_frame;
+
+typedef struct psfs_batch psfs_batch;  /* opaque */
+
+/* Plans a batch of nframes (1..65536) frames of uneven shapes processed by two
+ * persistent launches (likelihood maps of every view of every frame, then
+ * fusion of every frame, frames in decreasing voxels x views order) whose
+ * workgroups pull work items from device counters. The launches are captured
+ * into a HIP graph on the first run and replayed afterwards. Every frame's
+ * result is bit-identical to psfs_reconstruct of that frame alone (same
+ * params). Uses params.sampling (nearest, or the bilinear posterior).
+ * Allocates a device descriptor table and a pinned host staging copy on the
+ * current device; psfs_batch_destroy frees them. */
+int psfs_batch_create(psfs_batch **out, const psfs_params *params, int nframes,
+                      const psfs_frame *frames);
+size_t psfs_batch_workspace_bytes(const psfs_batch *batch);
+/* Runs the batch on `stream`: uploads the descriptor table if it changed,
+ * then replays the captured graph (captured on the first run, and again when
+ * the workspace pointer or the tile changes). On the null stream, or on a
+ * stream the caller is capturing, the kernels are launched directly. Runs of
+ * one batch must be ordered (one stream, or synchronised by the caller); they
+ * share the workspace, which holds the likelihood maps and two counters. Must
+ * run on the device the batch was created on (PSFS_E_DEVICE otherwise). */
+int psfs_batch_run(psfs_batch *batch, void *workspace_dev, size_t workspace_bytes, void *stream);
+/* Replaces the frames' pointers, camera matrices and grid placement (origin,
+ * voxel size). The shape signature (frame count, per-frame grid dims, view
+ * counts and image sizes) must be unchanged (PSFS_E_STALE otherwise); the
+ * captured graph is then reused and only the descriptor table is re-sent. */
+int psfs_batch_update(psfs_batch *batch, int nframes, const psfs_frame *frames);
+/* Waits for the batch's outstanding work on the device, then frees it. NULL-safe. */
+void psfs_batch_destroy(psfs_batch *batch);
+
+/* Fusion tile of the batch (index into the tile table below; -1 = default). */
+int psfs_batch_set_tile(psfs_batch *batch, int tile);
+int psfs_batch_get_tile(const psfs_batch *batch);
+
+/* Autotuner: times every fusion tile on this batch (2 warm-up + 5 timed runs
+ * each, HIP events on `stream`, blocking) and keeps the fastest. The choice is
+ * cached on disk as JSON keyed by device, CU count, sampling and a hash of the
+ * shape signature (file: $PSFS_AUTOTUNE_CACHE, else
+ * $HOME/.cache/psfs/autotune.json); a cached choice is reused without timing
+ * unless force != 0. Tiles never change results, only speed. */
+int psfs_batch_tune(psfs_batch *batch, void *workspace_dev, size_t workspace_bytes, void *stream, int force,
+                    int *best_tile);
+
+
 /* Kernel variant selection used by the batch and forward paths:
  * tile = index into the library's fusion tile table (see psfs_tile_count),
  * or -1 for the tuned/default choice. */

@@ -34,6 +34,12 @@ class psfs_params(C.Structure):
                 ("sampling", C.c_int32)]
 
 
+class psfs_frame(C.Structure):
+    _fields_ = [("grid", psfs_grid), ("n", C.c_int32), ("cams", C.POINTER(psfs_camera)),
+                ("images_dev", C.POINTER(C.c_void_p)), ("mean_dev", C.POINTER(C.c_void_p)),
+                ("var_dev", C.POINTER(C.c_void_p)), ("posterior_dev", C.c_void_p), ("occ_dev", C.c_void_p)]
+
+
 class PsfsError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -68,6 +74,14 @@ SIGNATURES = {
     "psfs_diff_forward": (C.c_int, [vp, C.POINTER(vp), vp, i32p, vp, vp, vp, C.c_size_t, vp]),
     "psfs_diff_backward": (C.c_int, [vp, C.POINTER(vp), vp, i32p, vp, vp, C.POINTER(vp), C.POINTER(vp), vp, vp,
                                      C.c_size_t, vp]),
+    "psfs_batch_create": (C.c_int, [C.POINTER(vp), C.POINTER(psfs_params), C.c_int, C.POINTER(psfs_frame)]),
+    "psfs_batch_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_batch_run": (C.c_int, [vp, vp, C.c_size_t, vp]),
+    "psfs_batch_update": (C.c_int, [vp, C.c_int, C.POINTER(psfs_frame)]),
+    "psfs_batch_destroy": (None, [vp]),
+    "psfs_batch_set_tile": (C.c_int, [vp, C.c_int]),
+    "psfs_batch_get_tile": (C.c_int, [vp]),
+    "psfs_batch_tune": (C.c_int, [vp, vp, C.c_size_t, vp, C.c_int, i32p]),
     "psfs_tile_count": (C.c_int, []),
     "psfs_tile_describe": (C.c_int, [C.c_int, i32p, i32p, i32p]),
     "psfs_set_tile": (C.c_int, [vp, C.c_int]),

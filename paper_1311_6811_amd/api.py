@@ -239,6 +239,85 @@ class Plan:
         return gmeans, gvars, gP[: self.n]
 
 
+class BatchFrame:
+    """One frame of a batch: cameras, grid, device images/background, outputs."""
+
+    def __init__(self, cams, grid, images, means, vars_, posterior=None, occ=None, want_occ=True):
+        self.cams, self.grid = list(cams), grid
+        self.images, self.means, self.vars = list(images), list(means), list(vars_)
+        shape = (grid.nz, grid.ny, grid.nx)
+        self.posterior = posterior if posterior is not None else torch.empty(shape, dtype=torch.float32, device="cuda")
+        self.occ = occ if occ is not None else (torch.empty(shape, dtype=torch.uint8, device="cuda") if want_occ else None)
+
+
+class Batch:
+    """Many frames of uneven shape in two persistent launches replayed from a
+    HIP graph (see psfs_batch_* in psfs.h)."""
+
+    def __init__(self, frames: Sequence[BatchFrame], prior=0.5, log_u=LOG_U_DEFAULT, threshold=0.5,
+                 sampling: int = L.NEAREST):
+        self._params = L.psfs_params(float(prior), float(log_u), float(threshold), int(sampling))
+        arr, keep = self._marshal(frames)
+        h = C.c_void_p()
+        L.check(L.lib().psfs_batch_create(C.byref(h), C.byref(self._params), len(frames), arr))
+        self._h, self._keep, self.frames = h, keep, list(frames)
+        self.workspace = torch.empty(max(int(L.lib().psfs_batch_workspace_bytes(h)), 256), dtype=torch.uint8,
+                                     device="cuda")
+
+    @staticmethod
+    def _marshal(frames):
+        arr = (L.psfs_frame * len(frames))()
+        keep = []
+        for f, fr in enumerate(frames):
+            n = len(fr.cams)
+            cams = (L.psfs_camera * n)(*[make_camera(c.width, c.height, c.P) for c in fr.cams])
+            ims = L.ptr_array([_dev(im, torch.uint8, f"frame {f} image {k}", (c.height, c.width, 3))
+                               for k, (im, c) in enumerate(zip(fr.images, fr.cams))])
+            mus = L.ptr_array([_dev(m, torch.float32, f"frame {f} mean {k}", (c.height, c.width, 3))
+                               for k, (m, c) in enumerate(zip(fr.means, fr.cams))])
+            vs = L.ptr_array([_dev(v, torch.float32, f"frame {f} var {k}", (c.height, c.width, 3))
+                              for k, (v, c) in enumerate(zip(fr.vars, fr.cams))])
+            g = fr.grid
+            shape = (g.nz, g.ny, g.nx)
+            arr[f].grid = make_grid(g.nx, g.ny, g.nz, g.origin, g.voxel)
+            arr[f].n = n
+            arr[f].cams = cams
+            arr[f].images_dev = ims
+            arr[f].mean_dev = mus
+            arr[f].var_dev = vs
+            arr[f].posterior_dev = _dev(fr.posterior, torch.float32, f"frame {f} posterior", shape)
+            arr[f].occ_dev = _dev(fr.occ, torch.uint8, f"frame {f} occ", shape) if fr.occ is not None else None
+            keep.append((cams, ims, mus, vs, fr))
+        return arr, keep
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib().psfs_batch_destroy(h)
+            self._h = None
+
+    def run(self) -> None:
+        L.check(L.lib().psfs_batch_run(self._h, self.workspace.data_ptr(), self.workspace.numel(), _stream()))
+
+    def update(self, frames: Sequence[BatchFrame]) -> None:
+        arr, keep = self._marshal(frames)
+        L.check(L.lib().psfs_batch_update(self._h, len(frames), arr))
+        self._keep, self.frames = keep, list(frames)
+
+    def set_tile(self, tile: int) -> None:
+        L.check(L.lib().psfs_batch_set_tile(self._h, int(tile)))
+
+    @property
+    def tile(self) -> int:
+        return L.check(L.lib().psfs_batch_get_tile(self._h))
+
+    def tune(self, force: bool = False) -> int:
+        best = C.c_int32(-1)
+        L.check(L.lib().psfs_batch_tune(self._h, self.workspace.data_ptr(), self.workspace.numel(), _stream(),
+                                        int(force), C.byref(best)))
+        return best.value
+
+
 def tiles():
     n = L.lib().psfs_tile_count()
     out = []

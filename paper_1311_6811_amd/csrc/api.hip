@@ -9,7 +9,7 @@
 #include <new>
 #include <string>
 
-#include "psfs_internal.h"
+#include "host_util.h"
 
 struct psfs_plan {
     int n = -1;                                     // -1: cameras not set
@@ -23,7 +23,7 @@ struct psfs_plan {
 };
 
 namespace psfs {
-namespace {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -73,6 +73,20 @@ int check_device()
     state[dev] = 1;
     return PSFS_OK;
 }
+
+int64_t padded_pixels(int width, int height)
+{
+    const int64_t np = static_cast<int64_t>(width) * height;
+    return (np + kMapAlignFloats - 1) / kMapAlignFloats * kMapAlignFloats;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace host
+
+namespace {
+
+using namespace host;
 
 int64_t map_floats(const psfs_plan *p)
 {
@@ -203,8 +217,6 @@ struct DiffLayout {
     size_t lmap, adj, loss, cam, total;
 };
 
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-
 DiffLayout diff_layout(const psfs_plan *p)
 {
     DiffLayout L{};
@@ -265,12 +277,8 @@ int prepare_diff(const psfs_plan *p, const uint8_t *const *images, const uint8_t
 }  // namespace psfs
 
 using namespace psfs;
+using namespace psfs::host;
 
-#define PSFS_GUARD_BEGIN try {
-#define PSFS_GUARD_END                                                    \
-    }                                                                     \
-    catch (const std::bad_alloc &) { return fail(PSFS_E_RANGE, "out of host memory"); } \
-    catch (...) { return fail(PSFS_E_ARG, "unexpected exception"); }
 
 extern "C" {
 
@@ -291,7 +299,7 @@ const char *psfs_status_str(int status)
     }
 }
 
-const char *psfs_last_error(void) { return g_last_error.c_str(); }
+const char *psfs_last_error(void) { return psfs::host::g_last_error.c_str(); }
 
 void psfs_default_params(psfs_params *out)
 {

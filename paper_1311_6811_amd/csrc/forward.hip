@@ -54,10 +54,7 @@ __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
 
 // Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,
 // 64-lane waves are TX x (64/TX) slabs, one voxel thick in z) and KZ
-// consecutive z-slices; each lane owns one column segment of KZ voxels and
-// loops over the views in order k = 0..n-1, so every tile shape produces the
-// same bits. The z-independent part of each projection row is computed once
-// per lane and view.
+// consecutive z-slices; each lane owns one column segment of KZ voxels.
 template <int TX, int TY, int KZ, int SAMPLING>
 __global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
 {
@@ -71,73 +68,9 @@ __global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
     const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
     const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
     const int k0 = static_cast<int>(zc) * KZ;
-
-    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
-    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
-    float Z[KZ], L[KZ];
-#pragma unroll
-    for (int kk = 0; kk < KZ; ++kk) {
-        Z[kk] = a.oz + a.h * (static_cast<float>(k0 + kk) + 0.5f);
-        L[kk] = a.L0;
-    }
-
-    if (SAMPLING == PSFS_NEAREST) {
-        for (int v = 0; v < a.n; ++v) {
-            const ViewGeom &g = a.view[v];
-            const float *map = a.lmap + g.map_off;
-            const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
-            const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
-            const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
-#pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const float c = fmaf(g.P[10], Z[kk], cx);
-                const float r = __builtin_amdgcn_rcpf(c);
-                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
-                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
-                if (c > 0.0f && static_cast<unsigned>(x) < static_cast<unsigned>(g.W) &&
-                    static_cast<unsigned>(y) < static_cast<unsigned>(g.H))
-                    L[kk] += map[static_cast<int64_t>(y) * g.W + x];
-            }
-        }
-    } else {
-        // Bilinear weights turn a projection error du into an error
-        // du * (l10 - l00) of the sample, and FP32 cannot place u closer than
-        // ~3e-5 px at u ~ 640. The projection is therefore evaluated in FP64
-        // (full rate on CDNA4, like unpacked FP32), from the FP64 voxel centre.
-        const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (i + 0.5);
-        const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (j + 0.5);
-        for (int v = 0; v < a.n; ++v) {
-            const ViewGeom &g = a.view[v];
-            const float *map = a.lmap + g.map_off;
-            const double ax = fma(static_cast<double>(g.P[0]), Xd, fma(static_cast<double>(g.P[1]), Yd, static_cast<double>(g.P[3])));
-            const double bx = fma(static_cast<double>(g.P[4]), Xd, fma(static_cast<double>(g.P[5]), Yd, static_cast<double>(g.P[7])));
-            const double cx = fma(static_cast<double>(g.P[8]), Xd, fma(static_cast<double>(g.P[9]), Yd, static_cast<double>(g.P[11])));
-#pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (k0 + kk + 0.5);
-                const double c = fma(static_cast<double>(g.P[10]), Zd, cx);
-                if (!(c > 0.0)) continue;
-                const double r = 1.0 / c;
-                const double u = fma(static_cast<double>(g.P[2]), Zd, ax) * r;
-                const double w = fma(static_cast<double>(g.P[6]), Zd, bx) * r;
-                const double x0 = floor(u), y0 = floor(w);
-                const float fx = static_cast<float>(u - x0), fy = static_cast<float>(w - y0);
-                L[kk] += bilinear_sample(map, g.W, g.H, x0, y0, fx, fy);
-            }
-        }
-    }
-
-    if (i >= a.nx || j >= a.ny) return;
-#pragma unroll
-    for (int kk = 0; kk < KZ; ++kk) {
-        const int k = k0 + kk;
-        if (k < a.nz) {
-            const int64_t idx = (static_cast<int64_t>(k) * a.ny + j) * a.nx + i;
-            const float p = 1.0f / (1.0f + expf(-L[kk]));
-            a.post[idx] = p;
-            if (a.occ) a.occ[idx] = p > a.tau ? 1 : 0;
-        }
-    }
+    const GridDesc gd{a.nx, a.ny, a.nz, a.ox, a.oy, a.oz, a.h};
+    fuse_column<KZ, SAMPLING>([&](int v) -> const ViewGeom & { return a.view[v]; }, a.n, a.lmap, gd, i, j, k0,
+                              a.L0, a.tau, a.post, a.occ);
 }
 
 __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)

@@ -88,5 +88,84 @@ __device__ __forceinline__ Proj64 proj64_column(const ViewGeom &g, double X, dou
     return p;
 }
 
+// Eq. 3-9 for one lane's column segment of KZ voxels, (i, j, k0..k0+KZ-1):
+// for every view in order k = 0..n-1, project the voxel centre, read the view's
+// log(2*SLM) at the nearest pixel (or bilinearly) and add it to the logit;
+// then posterior = sigmoid(logit) and occupancy = posterior > tau. The view
+// order is fixed, so every lane layout and work decomposition produces the
+// same bits. views(v) returns the ViewGeom of view v (P pre-offset by half of
+// row 2 for nearest sampling).
+template <int KZ, int SAMPLING, class Views>
+__device__ __forceinline__ void fuse_column(const Views &views, int n, const float *lmap, const GridDesc &a, int i,
+                                            int j, int k0, float L0, float tau, float *post, uint8_t *occ)
+{
+    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
+    float Z[KZ], L[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        Z[kk] = a.oz + a.h * (static_cast<float>(k0 + kk) + 0.5f);
+        L[kk] = L0;
+    }
+
+    if (SAMPLING == PSFS_NEAREST) {
+        for (int v = 0; v < n; ++v) {
+            const ViewGeom &g = views(v);
+            const float *map = lmap + g.map_off;
+            const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+            const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+            const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float c = fmaf(g.P[10], Z[kk], cx);
+                const float r = __builtin_amdgcn_rcpf(c);
+                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                if (c > 0.0f && static_cast<unsigned>(x) < static_cast<unsigned>(g.W) &&
+                    static_cast<unsigned>(y) < static_cast<unsigned>(g.H))
+                    L[kk] += map[static_cast<int64_t>(y) * g.W + x];
+            }
+        }
+    } else {
+        // Bilinear weights turn a projection error du into an error
+        // du * (l10 - l00) of the sample, and FP32 cannot place u closer than
+        // ~3e-5 px at u ~ 640. The projection is therefore evaluated in FP64
+        // (full rate on CDNA4, like unpacked FP32), from the FP64 voxel centre.
+        const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (i + 0.5);
+        const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (j + 0.5);
+        for (int v = 0; v < n; ++v) {
+            const ViewGeom &g = views(v);
+            const float *map = lmap + g.map_off;
+            const double ax = fma(static_cast<double>(g.P[0]), Xd, fma(static_cast<double>(g.P[1]), Yd, static_cast<double>(g.P[3])));
+            const double bx = fma(static_cast<double>(g.P[4]), Xd, fma(static_cast<double>(g.P[5]), Yd, static_cast<double>(g.P[7])));
+            const double cx = fma(static_cast<double>(g.P[8]), Xd, fma(static_cast<double>(g.P[9]), Yd, static_cast<double>(g.P[11])));
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (k0 + kk + 0.5);
+                const double c = fma(static_cast<double>(g.P[10]), Zd, cx);
+                if (!(c > 0.0)) continue;
+                const double r = 1.0 / c;
+                const double u = fma(static_cast<double>(g.P[2]), Zd, ax) * r;
+                const double w = fma(static_cast<double>(g.P[6]), Zd, bx) * r;
+                const double x0 = floor(u), y0 = floor(w);
+                const float fx = static_cast<float>(u - x0), fy = static_cast<float>(w - y0);
+                L[kk] += bilinear_sample(map, g.W, g.H, x0, y0, fx, fy);
+            }
+        }
+    }
+
+    if (i >= a.nx || j >= a.ny) return;
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        const int k = k0 + kk;
+        if (k < a.nz) {
+            const int64_t idx = (static_cast<int64_t>(k) * a.ny + j) * a.nx + i;
+            const float p = 1.0f / (1.0f + expf(-L[kk]));
+            post[idx] = p;
+            if (occ) occ[idx] = p > tau ? 1 : 0;
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace psfs

@@ -39,6 +39,11 @@ struct ViewGeom {
     int64_t map_off;
 };
 
+struct GridDesc {
+    int nx, ny, nz;
+    float ox, oy, oz, h;                // grid origin (corner) and voxel edge
+};
+
 struct FuseArgs {
     ViewGeom view[kMaxViews];
     const float *lmap;
@@ -86,6 +91,34 @@ struct ChainArgs {
     int32_t n;
 };
 
+// Batched pass: one device descriptor table of views and frames.
+struct BatchView {
+    ViewGeom g;                         // map_off indexes the batch's map arena
+    const uint8_t *img;
+    const float *mean;
+    const float *var;
+    int64_t npix;
+    int64_t chunk0;                     // first likelihood-map chunk of this view
+};
+
+struct BatchFrame {
+    GridDesc grid;
+    int32_t n, view0;                   // views [view0, view0 + n) of the table
+    int64_t brick0;                     // first fusion brick of this frame
+    float *post;
+    uint8_t *occ;                       // nullable
+};
+
+struct BatchArgs {
+    const BatchView *views;
+    const BatchFrame *frames;           // decreasing cost order
+    float *lmap;
+    unsigned long long *counters;       // [0] chunks popped, [1] bricks popped
+    int64_t nchunks, nbricks;
+    int32_t nviews, nframes;
+    float k0, L0, tau;
+};
+
 struct TileCfg {
     int tx, ty, kz;                     // x-by-y lanes per workgroup, z voxels per lane
 };
@@ -101,6 +134,10 @@ int64_t diff_bwd_blocks(int nx, int ny, int nz);
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);
 hipError_t launch_diff_backward(const DiffArgs &a, const ChainArgs &c, int64_t map_floats, int64_t max_npix,
                                 float *gP, hipStream_t s);
+int64_t batch_chunk_pixels();
+int64_t batch_bricks(int nx, int ny, int nz, int tile);
+int batch_fuse_occupancy(int tile, int sampling);
+hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid, int fuse_grid, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 
 }  // namespace psfs

@@ -187,22 +187,42 @@ def make_body(rng: np.random.Generator, shift=(0.0, 0.0, 0.0)) -> List[Ellipsoid
     return parts
 
 
+def _ellipsoid_bbox(cam: Camera, e: Ellipsoid):
+    """Pixel box containing the ellipsoid's image: the projection of a convex
+    set in front of the camera lies in the hull of its bounding cube's
+    projected corners. None if the cube is not wholly in front."""
+    R = float(np.max(e.axes))
+    corners = e.centre + R * np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)])
+    xc = (corners - cam.C) @ cam.R.T
+    if np.any(xc[:, 2] <= 1e-9):
+        return None
+    u = cam.K[0, 0] * xc[:, 0] / xc[:, 2] + cam.K[0, 2]
+    v = cam.K[1, 1] * xc[:, 1] / xc[:, 2] + cam.K[1, 2]
+    x0, x1 = int(np.floor(u.min())) - 1, int(np.ceil(u.max())) + 2
+    y0, y1 = int(np.floor(v.min())) - 1, int(np.ceil(v.max())) + 2
+    return max(x0, 0), min(x1, cam.width), max(y0, 0), min(y1, cam.height)
+
+
 def render_mask(cam: Camera, body: Sequence[Ellipsoid]) -> np.ndarray:
     """Exact FP64 silhouette: rays through integer pixel centres vs ellipsoids."""
     W, H = cam.width, cam.height
-    x, y = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
-    f, cx, cy = cam.K[0, 0], cam.K[0, 2], cam.K[1, 2]
-    dc = np.stack([(x - cx) / f, (y - cy) / cam.K[1, 1], np.ones_like(x)], axis=-1)
-    d = dc @ cam.R                    # world ray directions, R^T applied row-wise
     mask = np.zeros((H, W), bool)
+    f, cx, cy = cam.K[0, 0], cam.K[0, 2], cam.K[1, 2]
     for e in body:
+        box = _ellipsoid_bbox(cam, e)
+        x0, x1, y0, y1 = (0, W, 0, H) if box is None else box
+        if x0 >= x1 or y0 >= y1:
+            continue
+        x, y = np.meshgrid(np.arange(x0, x1, dtype=np.float64), np.arange(y0, y1, dtype=np.float64))
+        dc = np.stack([(x - cx) / f, (y - cy) / cam.K[1, 1], np.ones_like(x)], axis=-1)
+        d = dc @ cam.R                # world ray directions, R^T applied row-wise
         M = e.rot.T / e.axes[:, None]  # world -> unit-sphere frame (linear part)
         c0 = M @ (cam.C - e.centre)
         dd = d @ M.T
         A = np.einsum("hwk,hwk->hw", dd, dd)
         B = dd @ c0
         Cc = c0 @ c0 - 1.0
-        mask |= (B * B - A * Cc >= 0.0) & (B < 0.0)
+        mask[y0:y1, x0:x1] |= (B * B - A * Cc >= 0.0) & (B < 0.0)
     return mask
 
 
@@ -222,8 +242,8 @@ def gt_occupancy(grid: Grid, body: Sequence[Ellipsoid]) -> np.ndarray:
 # ------------------------------------------------------------- background/images
 
 def make_background(rng: np.random.Generator, H: int, W: int):
-    mean = rng.uniform(0.0, 255.0, (H, W, 3))
-    std = rng.uniform(5.0, 15.0, (H, W, 3))
+    mean = 255.0 * rng.random((H, W, 3), dtype=np.float32)
+    std = 5.0 + 10.0 * rng.random((H, W, 3), dtype=np.float32)
     return mean.astype(np.float32), (std * std).astype(np.float32)
 
 
@@ -231,12 +251,13 @@ def render_image(mask: np.ndarray, mean: np.ndarray, var: np.ndarray,
                  rng_noise: np.random.Generator, rng_fg: np.random.Generator,
                  rng_out: np.random.Generator, outlier_rate: float = 0.02) -> np.ndarray:
     H, W = mask.shape
-    std = np.sqrt(var.astype(np.float64))
-    bg = np.clip(np.round(mean.astype(np.float64) + std * rng_noise.normal(size=(H, W, 3))), 0, 255)
-    fg = np.clip(np.round(rng_fg.uniform(0.0, 255.0, (H, W, 3)) + rng_fg.normal(0.0, 10.0, (H, W, 3))), 0, 255)
+    std = np.sqrt(var)
+    bg = np.clip(np.round(mean + std * rng_noise.standard_normal((H, W, 3), dtype=np.float32)), 0, 255)
+    fg = np.clip(np.round(255.0 * rng_fg.random((H, W, 3), dtype=np.float32)
+                          + 10.0 * rng_fg.standard_normal((H, W, 3), dtype=np.float32)), 0, 255)
     img = np.where(mask[..., None], fg, bg)
-    hit = rng_out.random((H, W)) < outlier_rate
-    white = rng_out.random((H, W)) < 0.5
+    hit = rng_out.random((H, W), dtype=np.float32) < outlier_rate
+    white = rng_out.random((H, W), dtype=np.float32) < 0.5
     img[hit & white] = 255.0
     img[hit & ~white] = 0.0
     return img.astype(np.uint8)

@@ -206,3 +206,30 @@ def test_diff_validation_without_device(lib):
     assert lib.psfs_diff_backward(h, imgs, fake, None, fake, fake, L.ptr_array([0x100000, 0x100004]),
                                   L.ptr_array([0x100000] * 2), fake, ws, need, None) == -1
     lib.psfs_plan_destroy(h)
+
+
+def test_batch_validation_without_device(lib):
+    params = L.psfs_params()
+    lib.psfs_default_params(C.byref(params))
+    h = C.c_void_p()
+    assert lib.psfs_batch_create(C.byref(h), C.byref(params), 0, None) == -2
+    assert lib.psfs_batch_create(C.byref(h), C.byref(params), 1, None) == -1
+    cams = (L.psfs_camera * 1)(_cam(8, 6))
+    ptrs = L.ptr_array([0x100000])
+    fr = (L.psfs_frame * 1)()
+    fr[0].grid = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    fr[0].n = 0
+    assert lib.psfs_batch_create(C.byref(h), C.byref(params), 1, fr) == -2       # no views
+    fr[0].n = 1
+    fr[0].cams, fr[0].images_dev, fr[0].mean_dev, fr[0].var_dev = cams, ptrs, ptrs, ptrs
+    fr[0].posterior_dev = None
+    assert lib.psfs_batch_create(C.byref(h), C.byref(params), 1, fr) == -1       # posterior NULL
+    fr[0].posterior_dev = 0x100000
+    fr[0].images_dev = L.ptr_array([0x100002])
+    assert lib.psfs_batch_create(C.byref(h), C.byref(params), 1, fr) == -1       # image misaligned
+    bad = L.psfs_params(0.5, -1.0, 0.5, 3)
+    assert lib.psfs_batch_create(C.byref(h), C.byref(bad), 1, fr) == -1
+    assert lib.psfs_batch_workspace_bytes(None) == 0
+    assert lib.psfs_batch_set_tile(None, 0) == -1
+    assert lib.psfs_batch_run(None, None, 0, None) == -1
+    lib.psfs_batch_destroy(None)
