@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=int, default=-1)
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiable fwd / fwd+bwd measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame uneven batch measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -54,6 +58,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     psfs.lib()          # fail loudly if the HIP library is missing
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)         # elementwise: reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     # ------------------------------------------------------------ inputs
     t0 = time.time()
@@ -127,6 +138,27 @@ def main():
             torch.cuda.synchronize()
             return e0.elapsed_time(e1) / steps, steps
 
+    def timed_graph(fns, reps, warmup):
+        """Average ms of one pass over fns (a cycle of calls) replayed from a graph."""
+        with torch.cuda.stream(stream):
+            for f in fns:
+                f()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for f in fns:
+                    f()
+            for _ in range(warmup):
+                g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                g.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / (reps * len(fns))
+
     graph = not args.eager
     steps = (args.steps // len(slots)) * len(slots) if graph else args.steps
     steps = max(steps, len(slots))
@@ -155,6 +187,9 @@ def main():
     else:
         dom, dom_ms, dom_bytes = "fuse_kernel", ms_f, bytes_fuse
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+
+    diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
+    batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
@@ -198,9 +233,88 @@ def main():
                           "achieved_GBs": (27 * npix + 5 * V) / (ms * 1e-3) / 1e9,
                           "frac": (27 * npix + 5 * V) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "parity_max_abs_err": max_err,
+        "fwd_bwd": diff,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
+    """Differentiable pass on the 128^3 x 8-view workload (bilinear sampling,
+    BCE against the ellipsoid occupancy, cameras perturbed 1 %): forward alone
+    vs forward + backward, per frame."""
+    slots = []
+    for s in range(nslots):
+        fr = S.config_frame(4, s)
+        cams = S.perturb_cameras(fr.cams, seed=(4, s))
+        plan = psfs.Plan(cams, fr.grid, sampling=psfs.BILINEAR)
+        mus = [torch.from_numpy(m).cuda() for m in fr.mean]
+        vs = [torch.from_numpy(v).cuda() for v in fr.var]
+        plan.set_backgrounds(mus, vs)
+        d = dict(plan=plan, ims=[torch.from_numpy(i).cuda() for i in fr.images], mus=mus, vs=vs,
+                 lab=torch.from_numpy(S.gt_occupancy(fr.grid, fr.body)).cuda(), ws=plan.new_diff_workspace(),
+                 logits=torch.empty((fr.grid.nz, fr.grid.ny, fr.grid.nx), dtype=torch.float32, device="cuda"),
+                 loss=torch.empty((), dtype=torch.float32, device="cuda"),
+                 gl=torch.ones((), dtype=torch.float32, device="cuda"),
+                 gm=[torch.empty_like(m) for m in mus], gv=[torch.empty_like(v) for v in vs],
+                 gP=torch.empty((len(cams), 3, 4), dtype=torch.float32, device="cuda"))
+        slots.append(d)
+    torch.cuda.synchronize()
+
+    def fwd(d):
+        return lambda: d["plan"].diff_forward(d["ims"], d["lab"], None, d["logits"], d["loss"], d["ws"])
+
+    def fwdbwd(d):
+        def f():
+            d["plan"].diff_forward(d["ims"], d["lab"], None, d["logits"], d["loss"], d["ws"])
+            d["plan"].diff_backward(d["ims"], d["lab"], d["logits"], d["gl"], d["ws"], None, d["gm"], d["gv"], d["gP"])
+        return f
+
+    reps = max(10, args.steps // (4 * nslots))
+    ms_f = timed_graph([fwd(d) for d in slots], reps, 3)
+    ms_fb = timed_graph([fwdbwd(d) for d in slots], reps, 3)
+    print(f"[bench] differentiable: fwd {ms_f * 1e3:.2f} us, fwd+bwd {ms_fb * 1e3:.2f} us", file=sys.stderr, flush=True)
+    return {"workload": "128^3 grid, 8 views 640x480, bilinear, BCE loss over the whole grid, cameras perturbed 1 %",
+            "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb, "ratio": ms_fb / ms_f, "target_ratio": 3.0}
+
+
+def measure_batch(torch, psfs, S, args, nframes=64):
+    """The 64-frame uneven batch (grid edge in {64,96,128,192}, 4..12 views,
+    three image sizes) as two persistent launches replayed from a HIP graph."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.time()
+    with ThreadPoolExecutor(8) as ex:
+        frames = list(ex.map(lambda f: S.config_frame(3, f), range(nframes)))
+    gen_s = time.time() - t0
+    bfs = []
+    for fr in frames:
+        bfs.append(psfs.BatchFrame(fr.cams, fr.grid, [torch.from_numpy(i).cuda() for i in fr.images],
+                                   [torch.from_numpy(m).cuda() for m in fr.mean],
+                                   [torch.from_numpy(v).cuda() for v in fr.var]))
+    vv = sum(fr.grid.nvox * fr.n for fr in frames)
+    px = sum(fr.npix for fr in frames)
+    vox = sum(fr.grid.nvox for fr in frames)
+    del frames
+    b = psfs.Batch(bfs)
+    tile = b.tune()
+    b.run()
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    algo = 27 * px + 5 * vox
+    print(f"[bench] batch of {nframes}: {ms:.3f} ms per run (tile {tile}, generated in {gen_s:.0f}s)",
+          file=sys.stderr, flush=True)
+    return {"workload": f"{nframes} uneven frames (grid edge 64..192, 4..12 views, 320x240..1280x720)",
+            "ms_per_run": ms, "frames_per_s": nframes / (ms * 1e-3), "voxel_view_per_s": vv / (ms * 1e-3),
+            "algorithmic_bytes": algo, "achieved_GBs": algo / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile": psfs.tiles()[tile]}
 
 
 if __name__ == "__main__":

@@ -71,7 +71,8 @@ enum psfs_sampling {
 /* One view: image size and the 3x4 projection (u*c, v*c, c) = P [X; 1].
  * A voxel is seen by the view when c > 0 and its pixel lies in the image. */
 typedef struct psfs_camera {
-    int32_t width, height;  /* 1..65535 each, width*height < 2^31 */
+    int32_t width, height;  /* 1..65535 each, width*height < 2^30 (byte offsets
+                               into one map fit in 32 bits) */
     float P[12];            /* row-major 3x4, finite */
 } psfs_camera;
 

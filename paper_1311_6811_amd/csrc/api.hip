@@ -331,7 +331,7 @@ int psfs_set_cameras(psfs_plan *plan, int n, const psfs_camera *cams)
     for (int k = 0; k < n; ++k) {
         const psfs_camera &c = cams[k];
         if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535 ||
-            static_cast<int64_t>(c.width) * c.height >= (int64_t(1) << 31))
+            static_cast<int64_t>(c.width) * c.height >= (int64_t(1) << 30))
             return fail(PSFS_E_RANGE, "view %d: image size %dx%d out of range", k, c.width, c.height);
         if (!finite_all(c.P, 12)) return fail(PSFS_E_RANGE, "view %d: camera matrix not finite", k);
     }

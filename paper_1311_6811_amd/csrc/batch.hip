@@ -116,7 +116,7 @@ __global__ __launch_bounds__(TX * TY) void batch_fuse_kernel(BatchArgs a)
             const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
             const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
             const BatchView *views = a.views + fr.view0;
-            fuse_column<KZ, SAMPLING>([&](int v) -> const ViewGeom & { return views[v].g; }, fr.n, a.lmap, fr.grid,
+            fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return views[v].g; }, fr.n, a.lmap, fr.grid,
                                       i, j, static_cast<int>(zc) * KZ, a.L0, a.tau, fr.post, fr.occ);
         }
     }
@@ -133,12 +133,12 @@ hipError_t launch_batch_fuse_s(const BatchArgs &a, int tile, int grid, hipStream
     const TileCfg &c = tile_cfg(tile);
     const dim3 g(static_cast<unsigned>(grid)), b(c.tx * c.ty);
     switch (tile) {
-    case 0: hipLaunchKernelGGL((batch_fuse_kernel<32, 8, 4, S>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((batch_fuse_kernel<32, 8, 2, S>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((batch_fuse_kernel<32, 8, 8, S>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((batch_fuse_kernel<16, 16, 4, S>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((batch_fuse_kernel<64, 4, 4, S>), g, b, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((batch_fuse_kernel<64, 4, 2, S>), g, b, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((batch_fuse_kernel<8, 32, 4, S>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((batch_fuse_kernel<8, 32, 8, S>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((batch_fuse_kernel<8, 16, 4, S>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((batch_fuse_kernel<8, 32, 2, S>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((batch_fuse_kernel<32, 8, 4, S>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((batch_fuse_kernel<16, 16, 4, S>), g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -163,12 +163,12 @@ int occupancy_s(int tile)
     hipError_t e = hipErrorInvalidValue;
     const int bs = c.tx * c.ty;
     switch (tile) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<32, 8, 4, S>, bs, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<32, 8, 2, S>, bs, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<32, 8, 8, S>, bs, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<16, 16, 4, S>, bs, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<64, 4, 4, S>, bs, 0); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<64, 4, 2, S>, bs, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<8, 32, 4, S>, bs, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<8, 32, 8, S>, bs, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<8, 16, 4, S>, bs, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<8, 32, 2, S>, bs, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<32, 8, 4, S>, bs, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_fuse_kernel<16, 16, 4, S>, bs, 0); break;
     default: break;
     }
     return (e == hipSuccess && blocks > 0) ? blocks : 1;

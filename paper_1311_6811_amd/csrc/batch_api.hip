@@ -60,7 +60,7 @@ int validate_frame(const psfs_frame &f, int idx)
     for (int k = 0; k < f.n; ++k) {
         const psfs_camera &c = f.cams[k];
         if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535 ||
-            static_cast<int64_t>(c.width) * c.height >= (int64_t(1) << 31))
+            static_cast<int64_t>(c.width) * c.height >= (int64_t(1) << 30))
             return fail(PSFS_E_RANGE, "frame %d view %d: image size out of range", idx, k);
         if (!finite_all(c.P, 12)) return fail(PSFS_E_RANGE, "frame %d view %d: camera matrix not finite", idx, k);
         if (!f.images_dev[k] || !aligned(f.images_dev[k], 4)) return fail(PSFS_E_ARG, "frame %d view %d: image pointer NULL or misaligned", idx, k);

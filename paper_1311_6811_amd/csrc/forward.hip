@@ -16,39 +16,72 @@ namespace {
 
 using namespace dev;
 
-// One lane converts 4 consecutive pixels: 12 image bytes (3 dwords) and 12
-// floats each of mean and variance (3 x 16 B), all naturally aligned.
+constexpr int kSlmQuads = 2;            // pixel quads per lane in slm_kernel
+
+struct Quad {
+    uint32_t w[3];
+    f32x4 m[3], v[3];
+};
+
+__device__ __forceinline__ void load_quad(const SlmView &sv, int64_t p0, Quad &q)
+{
+    const uint32_t *iw = reinterpret_cast<const uint32_t *>(sv.img + 3 * p0);
+    const f32x4 *mp = reinterpret_cast<const f32x4 *>(sv.mean + 3 * p0);
+    const f32x4 *vp = reinterpret_cast<const f32x4 *>(sv.var + 3 * p0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        q.w[r] = __builtin_nontemporal_load(iw + r);
+        q.m[r] = __builtin_nontemporal_load(mp + r);
+        q.v[r] = __builtin_nontemporal_load(vp + r);
+    }
+}
+
+__device__ __forceinline__ f32x4 quad_log2slm(const Quad &q, float k0)
+{
+    f32x4 r;
+    r.x = log2slm(byte_of(q.w[0], 0), byte_of(q.w[0], 1), byte_of(q.w[0], 2), q.m[0].x, q.m[0].y, q.m[0].z,
+                  q.v[0].x, q.v[0].y, q.v[0].z, k0);
+    r.y = log2slm(byte_of(q.w[0], 3), byte_of(q.w[1], 0), byte_of(q.w[1], 1), q.m[0].w, q.m[1].x, q.m[1].y,
+                  q.v[0].w, q.v[1].x, q.v[1].y, k0);
+    r.z = log2slm(byte_of(q.w[1], 2), byte_of(q.w[1], 3), byte_of(q.w[2], 0), q.m[1].z, q.m[1].w, q.m[2].x,
+                  q.v[1].z, q.v[1].w, q.v[2].x, k0);
+    r.w = log2slm(byte_of(q.w[2], 1), byte_of(q.w[2], 2), byte_of(q.w[2], 3), q.m[2].y, q.m[2].z, q.m[2].w,
+                  q.v[2].y, q.v[2].z, q.v[2].w, k0);
+    return r;
+}
+
+__device__ __forceinline__ void tail_pixels(const SlmView &sv, float *lmap, float k0, int64_t p0)
+{
+    for (int64_t p = p0; p < sv.npix; ++p) {
+        const uint8_t *I = sv.img + 3 * p;
+        const float *m = sv.mean + 3 * p, *v = sv.var + 3 * p;
+        lmap[sv.map_off + p] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], k0);
+    }
+}
+
+// A lane converts kSlmQuads groups of 4 consecutive pixels, kSlmQuads*256*4
+// pixels apart within the workgroup's span; each group is 12 image bytes
+// (3 dwords) and 12 floats each of mean and variance (3 x 16 B), naturally
+// aligned. All loads are issued before any arithmetic.
 __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
 {
     const SlmView sv = a.view[blockIdx.y];
-    const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
-    if (p0 >= sv.npix) return;
-    float *out = a.lmap + sv.map_off + p0;
-    if (p0 + 4 <= sv.npix) {
-        const uint32_t *iw = reinterpret_cast<const uint32_t *>(sv.img + 3 * p0);
-        const uint32_t w0 = __builtin_nontemporal_load(iw + 0);
-        const uint32_t w1 = __builtin_nontemporal_load(iw + 1);
-        const uint32_t w2 = __builtin_nontemporal_load(iw + 2);
-        const f32x4 *mp = reinterpret_cast<const f32x4 *>(sv.mean + 3 * p0);
-        const f32x4 *vp = reinterpret_cast<const f32x4 *>(sv.var + 3 * p0);
-        const f32x4 m0 = __builtin_nontemporal_load(mp + 0);
-        const f32x4 m1 = __builtin_nontemporal_load(mp + 1);
-        const f32x4 m2 = __builtin_nontemporal_load(mp + 2);
-        const f32x4 v0 = __builtin_nontemporal_load(vp + 0);
-        const f32x4 v1 = __builtin_nontemporal_load(vp + 1);
-        const f32x4 v2 = __builtin_nontemporal_load(vp + 2);
-        f32x4 r;
-        r.x = log2slm(byte_of(w0, 0), byte_of(w0, 1), byte_of(w0, 2), m0.x, m0.y, m0.z, v0.x, v0.y, v0.z, a.k0);
-        r.y = log2slm(byte_of(w0, 3), byte_of(w1, 0), byte_of(w1, 1), m0.w, m1.x, m1.y, v0.w, v1.x, v1.y, a.k0);
-        r.z = log2slm(byte_of(w1, 2), byte_of(w1, 3), byte_of(w2, 0), m1.z, m1.w, m2.x, v1.z, v1.w, v2.x, a.k0);
-        r.w = log2slm(byte_of(w2, 1), byte_of(w2, 2), byte_of(w2, 3), m2.y, m2.z, m2.w, v2.y, v2.z, v2.w, a.k0);
-        *reinterpret_cast<f32x4 *>(out) = r;
-    } else {
-        for (int64_t p = p0; p < sv.npix; ++p) {
-            const uint8_t *I = sv.img + 3 * p;
-            const float *m = sv.mean + 3 * p, *v = sv.var + 3 * p;
-            out[p - p0] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], a.k0);
-        }
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * 4 * kSlmQuads) + threadIdx.x * 4;
+    Quad q[kSlmQuads];
+    bool full[kSlmQuads];
+#pragma unroll
+    for (int t = 0; t < kSlmQuads; ++t) {
+        const int64_t p0 = base + t * 1024;
+        full[t] = p0 + 4 <= sv.npix;
+        if (full[t]) load_quad(sv, p0, q[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kSlmQuads; ++t) {
+        const int64_t p0 = base + t * 1024;
+        if (full[t])
+            *reinterpret_cast<f32x4 *>(a.lmap + sv.map_off + p0) = quad_log2slm(q[t], a.k0);
+        else if (p0 < sv.npix)
+            tail_pixels(sv, a.lmap, a.k0, p0);
     }
 }
 
@@ -69,7 +102,7 @@ __global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
     const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
     const int k0 = static_cast<int>(zc) * KZ;
     const GridDesc gd{a.nx, a.ny, a.nz, a.ox, a.oy, a.oz, a.h};
-    fuse_column<KZ, SAMPLING>([&](int v) -> const ViewGeom & { return a.view[v]; }, a.n, a.lmap, gd, i, j, k0,
+    fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return a.view[v]; }, a.n, a.lmap, gd, i, j, k0,
                               a.L0, a.tau, a.post, a.occ);
 }
 
@@ -81,7 +114,7 @@ __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64
 }
 
 constexpr TileCfg kTiles[] = {
-    {32, 8, 4}, {32, 8, 2}, {32, 8, 8}, {16, 16, 4}, {64, 4, 4}, {64, 4, 2},
+    {8, 32, 4}, {8, 32, 8}, {8, 16, 4}, {8, 32, 2}, {32, 8, 4}, {16, 16, 4},
 };
 
 template <int S>
@@ -92,12 +125,12 @@ hipError_t launch_fuse_s(const FuseArgs &a, int tile, hipStream_t s)
                        ((a.nz + c.kz - 1) / c.kz);
     const dim3 grid(static_cast<unsigned>(nb)), block(c.tx * c.ty);
     switch (tile) {
-    case 0: hipLaunchKernelGGL((fuse_kernel<32, 8, 4, S>), grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((fuse_kernel<32, 8, 2, S>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((fuse_kernel<32, 8, 8, S>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((fuse_kernel<16, 16, 4, S>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((fuse_kernel<64, 4, 4, S>), grid, block, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((fuse_kernel<64, 4, 2, S>), grid, block, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((fuse_kernel<8, 32, 4, S>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((fuse_kernel<8, 32, 8, S>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((fuse_kernel<8, 16, 4, S>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((fuse_kernel<8, 32, 2, S>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((fuse_kernel<32, 8, 4, S>), grid, block, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((fuse_kernel<16, 16, 4, S>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -111,8 +144,8 @@ int default_tile() { return 0; }
 
 hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s)
 {
-    const int64_t quads = (max_npix + 3) / 4;
-    const dim3 grid(static_cast<unsigned>((quads + 255) / 256), static_cast<unsigned>(a.n));
+    const int64_t per_block = 256 * 4 * kSlmQuads;
+    const dim3 grid(static_cast<unsigned>((max_npix + per_block - 1) / per_block), static_cast<unsigned>(a.n));
     hipLaunchKernelGGL(slm_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -10,25 +10,46 @@ constexpr float kLn2 = 0.693147180559945309f;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// 1/v to about half an ulp: hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ float recip(float v)
+{
+    const float r = __builtin_amdgcn_rcpf(v);
+    return fmaf(r, fmaf(-v, r, 1.0f), r);
+}
+
 // d = log N(I | mu, var) - log u of one pixel (Eq. 1), with
 // k0 = -1.5*log(2*pi) - log_u: d = k0 - 1/2 * (log(v0*v1*v2) + sum_c d_c^2/v_c).
+// The log-determinant uses the hardware log2 (about 1 ulp): its error enters
+// log(2*SLM) at ~1e-6 absolute or less, below the FP32 rounding of d itself.
 __device__ __forceinline__ float pixel_d(float i0, float i1, float i2, float m0, float m1, float m2,
                                         float v0, float v1, float v2, float k0)
 {
     const float d0 = i0 - m0, d1 = i1 - m1, d2 = i2 - m2;
-    const float q = d0 * d0 / v0 + d1 * d1 / v1 + d2 * d2 / v2;
-    const float half_logdet = 0.5f * (logf(v0 * v1) + logf(v2));
+    const float q = fmaf(d0 * d0, recip(v0), fmaf(d1 * d1, recip(v1), d2 * d2 * recip(v2)));
+    const float half_logdet = (0.5f * kLn2) * (__builtin_amdgcn_logf(v0 * v1) + __builtin_amdgcn_logf(v2));
     return (k0 - half_logdet) - 0.5f * q;
 }
 
 // log(2*SLM) = log 2 - softplus(d), since SLM = u/(u+N) = sigmoid(-d) (Eq. 1-2
-// with equal pixel priors).
+// with equal pixel priors). softplus(d) = max(d,0) + log(1 + e^-|d|) with the
+// hardware exp2/log2: 1 + e^-|d| lies in [1, 2], so the absolute error is a
+// few 1e-8.
 __device__ __forceinline__ float log2slm(float i0, float i1, float i2, float m0, float m1, float m2,
                                          float v0, float v1, float v2, float k0)
 {
+    constexpr float kLog2E = 1.44269504088896341f;
     const float d = pixel_d(i0, i1, i2, m0, m1, m2, v0, v1, v2, k0);
-    const float softplus = fmaxf(d, 0.0f) + log1pf(expf(-fabsf(d)));
+    const float e = __builtin_amdgcn_exp2f(-fabsf(d) * kLog2E);
+    const float softplus = fmaxf(d, 0.0f) + kLn2 * __builtin_amdgcn_logf(1.0f + e);
     return kLn2 - softplus;
+}
+
+// 1 / (1 + e^-x) with the hardware exp2 and reciprocal (a few ulp; e^-x
+// overflowing to +inf gives 0, as it should).
+__device__ __forceinline__ float sigmoid_fast(float x)
+{
+    constexpr float kLog2E = 1.44269504088896341f;
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-x * kLog2E));
 }
 
 // sigmoid(x) without overflow for either sign.
@@ -70,6 +91,20 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb)
     return (bid % kNumXcd) * per + bid / kNumXcd;
 }
 
+// Buffer resource over one view's likelihood map (gfx9 descriptor: raw,
+// no stride, bounds-checked against num_records bytes).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const float *map, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(map), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+
+// One float of a map; 0 when the byte offset is at or past num_records.
+__device__ __forceinline__ float map_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+
 // Projection rows of one view evaluated in FP64 at an FP64 voxel centre:
 // the z-independent part once per voxel column, then one FMA per row.
 struct Proj64 {
@@ -88,14 +123,54 @@ __device__ __forceinline__ Proj64 proj64_column(const ViewGeom &g, double X, dou
     return p;
 }
 
+// Bit v of the result is set when every voxel centre of this wave's box
+// [i_lo,i_hi] x [j_lo,j_hi] x [k_lo,k_hi] (phantom lanes past the grid edge
+// included) projects in view v with depth > 0 to a point at least 1/64 px
+// inside the image, in nearest-pixel coordinates u + 1/2, v + 1/2 (the P rows
+// are pre-offset). Perspective projection maps the box into the convex hull of
+// its projected corners, and the FP32 error of a lane's projection (~1e-4 px)
+// is far below the margin, so such a view needs no per-voxel bounds test.
+// Lane l tests corner (l & 7) of view (l >> 3) + 8*pass; n <= 16 views.
+template <class Views>
+__device__ __forceinline__ uint32_t wave_inside_mask(const Views &views, int n, const GridDesc &a, int i_lo,
+                                                     int i_hi, int j_lo, int j_hi, int k_lo, int k_hi)
+{
+    constexpr float kMargin = 1.0f / 64.0f;
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int corner = lane & 7;
+    const float X = a.ox + a.h * (static_cast<float>((corner & 1) ? i_hi : i_lo) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>((corner & 2) ? j_hi : j_lo) + 0.5f);
+    const float Z = a.oz + a.h * (static_cast<float>((corner & 4) ? k_hi : k_lo) + 0.5f);
+    uint32_t mask = 0;
+    for (int pass = 0; pass * 8 < n; ++pass) {
+        const int v = pass * 8 + (lane >> 3);
+        bool ok = true;
+        if (v < n) {
+            const ViewGeom &g = views(v);
+            const float c = fmaf(g.P[10], Z, fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11])));
+            const float u = fmaf(g.P[2], Z, fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]))) / c;
+            const float w = fmaf(g.P[6], Z, fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]))) / c;
+            ok = c > 0.0f && u >= kMargin && u <= static_cast<float>(g.W) - kMargin && w >= kMargin &&
+                 w <= static_cast<float>(g.H) - kMargin;
+        }
+        const uint64_t bad = __ballot(!ok);
+        for (int q = 0; q < 8; ++q) {
+            const int vv = pass * 8 + q;
+            if (vv < n && ((bad >> (8 * q)) & 0xffull) == 0) mask |= 1u << vv;
+        }
+    }
+    return mask;
+}
+
 // Eq. 3-9 for one lane's column segment of KZ voxels, (i, j, k0..k0+KZ-1):
 // for every view in order k = 0..n-1, project the voxel centre, read the view's
 // log(2*SLM) at the nearest pixel (or bilinearly) and add it to the logit;
 // then posterior = sigmoid(logit) and occupancy = posterior > tau. The view
-// order is fixed, so every lane layout and work decomposition produces the
-// same bits. views(v) returns the ViewGeom of view v (P pre-offset by half of
-// row 2 for nearest sampling).
-template <int KZ, int SAMPLING, class Views>
+// order is fixed and the fast and checked nearest paths pick the same pixel,
+// so every lane layout and work decomposition produces the same bits.
+// views(v) returns the ViewGeom of view v (P pre-offset by half of row 2 for
+// nearest sampling). The lanes of a wave form a TX x (64/TX) slab of columns.
+template <int TX, int KZ, int SAMPLING, class Views>
 __device__ __forceinline__ void fuse_column(const Views &views, int n, const float *lmap, const GridDesc &a, int i,
                                             int j, int k0, float L0, float tau, float *post, uint8_t *occ)
 {
@@ -109,21 +184,67 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
     }
 
     if (SAMPLING == PSFS_NEAREST) {
-        for (int v = 0; v < n; ++v) {
-            const ViewGeom &g = views(v);
-            const float *map = lmap + g.map_off;
-            const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
-            const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
-            const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+        const int lane = static_cast<int>(threadIdx.x & 63);
+        const int i_lo = i - (lane % TX), j_lo = j - (lane / TX);
+        const uint32_t inside = wave_inside_mask(views, n, a, i_lo, i_lo + TX - 1, j_lo, j_lo + 64 / TX - 1, k0,
+                                                 k0 + KZ - 1);
+        // Views are taken kVB at a time: all kVB*KZ byte offsets first, then
+        // all gathers, then the adds in view order, so a wave keeps up to
+        // kVB*KZ loads in flight. Gathers are raw buffer loads from the view's
+        // map (32-bit offsets, W*H < 2^30): a voxel-view outside its image
+        // gets an offset past the end, for which the hardware returns 0, i.e.
+        // adds nothing; a slot past the last view loads the same way.
+        constexpr int kVB = 4;
+        for (int v0 = 0; v0 < n; v0 += kVB) {
+            uint32_t off[kVB][KZ];
+            __amdgpu_buffer_rsrc_t rsrc[kVB];
 #pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const float c = fmaf(g.P[10], Z[kk], cx);
-                const float r = __builtin_amdgcn_rcpf(c);
-                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
-                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
-                if (c > 0.0f && static_cast<unsigned>(x) < static_cast<unsigned>(g.W) &&
-                    static_cast<unsigned>(y) < static_cast<unsigned>(g.H))
-                    L[kk] += map[static_cast<int64_t>(y) * g.W + x];
+            for (int q = 0; q < kVB; ++q) {
+                const int v = v0 + q;
+                if (v >= n) {
+                    rsrc[q] = rsrc[0];
+#pragma unroll
+                    for (int kk = 0; kk < KZ; ++kk) off[q][kk] = 0xFFFFFFFFu;
+                    continue;
+                }
+                const ViewGeom &g = views(v);
+                const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+                rsrc[q] = map_rsrc(lmap + g.map_off, W * H * 4u);
+                const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+                const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+                const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+                if (inside & (1u << v)) {
+                    // every lane lands inside the image: truncation is the floor
+#pragma unroll
+                    for (int kk = 0; kk < KZ; ++kk) {
+                        const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
+                        const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
+                        const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
+                        off[q][kk] = (__umul24(y, W) + x) * 4u;
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KZ; ++kk) {
+                        const float c = fmaf(g.P[10], Z[kk], cx);
+                        const float r = __builtin_amdgcn_rcpf(c);
+                        const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                        const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                        const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
+                        off[q][kk] = ok ? (__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)) * 4u
+                                        : 0xFFFFFFFFu;
+                    }
+                }
+            }
+            float val[kVB][KZ];
+#pragma unroll
+            for (int q = 0; q < kVB; ++q) {
+#pragma unroll
+                for (int kk = 0; kk < KZ; ++kk) val[q][kk] = map_load(rsrc[q], off[q][kk]);
+            }
+#pragma unroll
+            for (int q = 0; q < kVB; ++q) {
+#pragma unroll
+                for (int kk = 0; kk < KZ; ++kk) L[kk] += val[q][kk];
             }
         }
     } else {
@@ -136,17 +257,15 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
         for (int v = 0; v < n; ++v) {
             const ViewGeom &g = views(v);
             const float *map = lmap + g.map_off;
-            const double ax = fma(static_cast<double>(g.P[0]), Xd, fma(static_cast<double>(g.P[1]), Yd, static_cast<double>(g.P[3])));
-            const double bx = fma(static_cast<double>(g.P[4]), Xd, fma(static_cast<double>(g.P[5]), Yd, static_cast<double>(g.P[7])));
-            const double cx = fma(static_cast<double>(g.P[8]), Xd, fma(static_cast<double>(g.P[9]), Yd, static_cast<double>(g.P[11])));
+            const Proj64 p = proj64_column(g, Xd, Yd);
 #pragma unroll
             for (int kk = 0; kk < KZ; ++kk) {
                 const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (k0 + kk + 0.5);
-                const double c = fma(static_cast<double>(g.P[10]), Zd, cx);
+                const double c = fma(p.pz2, Zd, p.cx);
                 if (!(c > 0.0)) continue;
                 const double r = 1.0 / c;
-                const double u = fma(static_cast<double>(g.P[2]), Zd, ax) * r;
-                const double w = fma(static_cast<double>(g.P[6]), Zd, bx) * r;
+                const double u = fma(p.pz0, Zd, p.ax) * r;
+                const double w = fma(p.pz1, Zd, p.bx) * r;
                 const double x0 = floor(u), y0 = floor(w);
                 const float fx = static_cast<float>(u - x0), fy = static_cast<float>(w - y0);
                 L[kk] += bilinear_sample(map, g.W, g.H, x0, y0, fx, fy);
@@ -160,7 +279,7 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
         const int k = k0 + kk;
         if (k < a.nz) {
             const int64_t idx = (static_cast<int64_t>(k) * a.ny + j) * a.nx + i;
-            const float p = 1.0f / (1.0f + expf(-L[kk]));
+            const float p = sigmoid_fast(L[kk]);
             post[idx] = p;
             if (occ) occ[idx] = p > tau ? 1 : 0;
         }
