@@ -225,7 +225,7 @@ DiffLayout diff_layout(const psfs_plan *p)
     const int64_t nbb = p->has_grid ? diff_bwd_blocks(p->grid.nx, p->grid.ny, p->grid.nz) : 0;
     L.lmap = 0;
     L.adj = align256(maps);
-    L.loss = L.adj + align256(maps);
+    L.loss = L.adj + align256(2 * maps);            // int64 adjoint per pixel
     L.cam = L.loss + align256(static_cast<size_t>(nbf) * sizeof(double));
     L.total = L.cam + align256(static_cast<size_t>(nbb) * 12 * (p->n > 0 ? p->n : 0) * sizeof(float));
     return L;
@@ -510,6 +510,8 @@ int psfs_diff_backward(psfs_plan *plan, const uint8_t *const *images_dev, const 
     ChainArgs c{};
     c.n = plan->n;
     c.adj = a.adj;
+    c.grad_loss = grad_loss_dev;
+    c.inv_count = a.inv_count;
     c.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(plan->params.log_u));
     int64_t max_np = 0;
     for (int k = 0; k < plan->n; ++k) {
@@ -517,7 +519,7 @@ int psfs_diff_backward(psfs_plan *plan, const uint8_t *const *images_dev, const 
         c.view[k] = ChainView{images_dev[k], plan->mean[k], plan->var[k], gmean_dev[k], gvar_dev[k], np, map_offset(plan, k)};
         if (np > max_np) max_np = np;
     }
-    hipError_t e = launch_diff_backward(a, c, map_floats(plan), max_np, gP_dev, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_diff_backward(a, c, 2 * map_floats(plan), max_np, gP_dev, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "differentiable backward launch");
     return PSFS_OK;
     PSFS_GUARD_END

@@ -15,10 +15,14 @@
 //                 dd/dmu_c = (I_c - mu_c)/v_c,
 //                 dd/dv_c = (I_c - mu_c)^2/(2 v_c^2) - 1/(2 v_c).
 // Reductions of the loss and of the camera gradients run in a fixed order
-// (per-lane, wavefront shuffle tree, waves in order, workgroups in order in
-// FP64), so those two outputs are reproducible bit for bit. The adjoint maps
-// are accumulated with FP32 atomics, so the background gradients may differ
-// in the last bits between runs.
+// (per lane, a fixed wavefront butterfly, waves in order, workgroups in order
+// in FP64). The adjoint maps are accumulated in fixed point: every term
+// g_v * w satisfies |g_v * w| <= G = |grad_loss| / |region|, so it is rounded
+// to a multiple of 2^-E with 2^E * G <= 2^19; a workgroup's terms for one
+// pixel (at most 2048) then fit in int32 in LDS (integer LDS atomics, much
+// faster than FP32 ones on this GPU) and the global sums fit in int64 (at most
+// 2^31 terms). Integer sums do not depend on order, so all outputs are
+// reproducible bit for bit; the rounding error per term is <= 2^-20 G.
 #include <algorithm>
 
 #include "kernels_common.h"
@@ -28,28 +32,44 @@ namespace {
 
 using namespace dev;
 
-constexpr int kTX = 32, kTY = 8;        // workgroup = 32 x 8 voxel columns, 4 waves
-constexpr int kBlock = kTX * kTY;
+// Workgroup = 8 x 8 voxel columns x (4 * KZ) slices; its 4 waves each cover a
+// 4 x 4 group of columns and 4 interleaved z-slices (lane l: column
+// (l & 3, (l >> 2) & 3), slice (l >> 4) + 4 * kk for kk < KZ). A wave is thus a
+// 4 x 4 x 4 voxel block in every instruction, so at most ~4 of its lanes lie on
+// one viewing ray of a horizontal camera: few lanes share a pixel, which keeps
+// same-address LDS atomics in the adjoint scatter rare.
+constexpr int kBX = 8, kBY = 8;
+constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kFwdKZ = 4;
-constexpr int kBwdKZ = 4;
+constexpr int kBwdKZ = 8;
+constexpr int kBoxCap = 4096;           // floats of one view's pixel box staged in LDS
+constexpr int kStageIters = kBoxCap / kBlock;
 
 struct Coords {
-    int i, j, k0;
+    int i, j, kb, lz;                   // lane column, first slice of the workgroup, lane slice offset
+    int bi, bj;                         // first column of the workgroup
 };
 
 template <int KZ>
 __device__ __forceinline__ Coords block_coords(int nx, int ny, int nz)
 {
-    const int ntx = (nx + kTX - 1) / kTX, nty = (ny + kTY - 1) / kTY;
+    const int ntx = (nx + kBX - 1) / kBX, nty = (ny + kBY - 1) / kBY;
     const int64_t ntile = static_cast<int64_t>(ntx) * nty;
-    const int64_t nb = ntile * ((nz + KZ - 1) / KZ);
+    const int64_t nb = ntile * ((nz + 4 * KZ - 1) / (4 * KZ));
     const int64_t b = xcd_remap(blockIdx.x, nb);
     const int64_t zc = b / ntile;
     const int t = static_cast<int>(b - zc * ntile);
     const int tyi = t / ntx, txi = t - tyi * ntx;
-    return Coords{txi * kTX + static_cast<int>(threadIdx.x % kTX), tyi * kTY + static_cast<int>(threadIdx.x / kTX),
-                  static_cast<int>(zc) * KZ};
+    const int w = static_cast<int>(threadIdx.x >> 6), l = static_cast<int>(threadIdx.x & 63);
+    Coords c;
+    c.bi = txi * kBX;
+    c.bj = tyi * kBY;
+    c.i = c.bi + 4 * (w & 1) + (l & 3);
+    c.j = c.bj + 4 * (w >> 1) + ((l >> 2) & 3);
+    c.kb = static_cast<int>(zc) * 4 * KZ;
+    c.lz = l >> 4;
+    return c;
 }
 
 __device__ __forceinline__ bool in_region(const DiffArgs &a, int i, int j, int k)
@@ -69,11 +89,51 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the 64 lanes, the same in every lane, in a fixed order: butterflies
+// within each 16-lane row (quad_perm xor 1, xor 2, row rotations by 4 and 8),
+// then the four row sums.
+__device__ __forceinline__ float wave_total(float v)
+{
+    v += dpp<0xb1>(v);
+    v += dpp<0x4e>(v);
+    v += dpp<0x124>(v);
+    v += dpp<0x128>(v);
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// Exponent E of the adjoint fixed point (see the file comment); 0 when G is
+// 0 or not finite (every term is then 0 or the input invalid).
+// Two's-complement int32 as the uint64 addend of a signed int64 sum.
+__device__ __forceinline__ unsigned long long widen(int q)
+{
+    return static_cast<unsigned long long>(static_cast<long long>(q));
+}
+
+__device__ __forceinline__ int adjoint_exponent(float grad_loss, float inv_count)
+{
+    const float G = fabsf(grad_loss) * inv_count;
+    if (!(G > 0.0f) || !isfinite(G)) return 0;
+    int e;
+    frexpf(G, &e);                      // G < 2^e
+    return 19 - e;
+}
+
+// 1/c in FP64: hardware reciprocal and two Newton steps (about 1 ulp).
+__device__ __forceinline__ double rcp64(double c)
+{
+    double r = __builtin_amdgcn_rcp(c);
+    r = fma(r, fma(-c, r, 1.0), r);
+    return fma(r, fma(-c, r, 1.0), r);
 }
 
 // One view's projection of a voxel centre, in FP64 (see the forward kernel).
@@ -87,7 +147,7 @@ __device__ __forceinline__ bool project64(const Proj64 &p, double Zd, Tap4 &t)
 {
     const double c = fma(p.pz2, Zd, p.cx);
     if (!(c > 0.0)) return false;
-    const double r = 1.0 / c;
+    const double r = rcp64(c);
     const double u = fma(p.pz0, Zd, p.ax) * r;
     const double w = fma(p.pz1, Zd, p.bx) * r;
     t.x0 = floor(u);
@@ -100,24 +160,137 @@ __device__ __forceinline__ bool project64(const Proj64 &p, double Zd, Tap4 &t)
     return true;
 }
 
+// Pixel box [x0, x0+w) x [y0, y0+h) holding both bilinear taps in x and y of
+// every voxel centre of the workgroup's voxel box, for every view: the
+// projection maps the box into the hull of its 8 projected corners (all in
+// front of the camera), widened by 1e-6 px for the lanes' own FP64 rounding.
+// Lanes 8v..8v+7 project the corners of view v; the box is stored in LDS.
+// ok = 0 when a corner is not in front or the box exceeds kBoxCap floats.
+struct PixBox {
+    int x0, y0, w, h, ok;
+};
+
+template <int KZ>
+__device__ __forceinline__ void compute_boxes(const DiffArgs &a, const Coords &q, PixBox *boxes)
+{
+    for (int t0 = 0; t0 < 8 * a.n; t0 += kBlock) {
+        const int t = t0 + static_cast<int>(threadIdx.x);
+        const int v = t < 8 * a.n ? t >> 3 : 0;
+        const int corner = t & 7;
+        const ViewGeom &g = a.view[v];
+        const double X = static_cast<double>(a.ox) + static_cast<double>(a.h) * ((corner & 1 ? q.bi + kBX - 1 : q.bi) + 0.5);
+        const double Y = static_cast<double>(a.oy) + static_cast<double>(a.h) * ((corner & 2 ? q.bj + kBY - 1 : q.bj) + 0.5);
+        const double Z = static_cast<double>(a.oz) + static_cast<double>(a.h) * ((corner & 4 ? q.kb + 4 * KZ - 1 : q.kb) + 0.5);
+        const Proj64 p = proj64_column(g, X, Y);
+        const double c = fma(p.pz2, Z, p.cx);
+        double ok = c > 0.0 ? 1.0 : 0.0;
+        const double u = fma(p.pz0, Z, p.ax) / c, w = fma(p.pz1, Z, p.bx) / c;
+        double umin = u, umax = u, wmin = w, wmax = w;
+#pragma unroll
+        for (int m = 1; m <= 4; m <<= 1) {
+            umin = fmin(umin, __shfl_xor(umin, m, 64));
+            umax = fmax(umax, __shfl_xor(umax, m, 64));
+            wmin = fmin(wmin, __shfl_xor(wmin, m, 64));
+            wmax = fmax(wmax, __shfl_xor(wmax, m, 64));
+            ok = fmin(ok, __shfl_xor(ok, m, 64));
+        }
+        if (t < 8 * a.n && corner == 0) {
+            PixBox b{0, 0, 0, 0, 0};
+            // NaN or huge coordinates fail these range tests
+            if (ok > 0.5 && umin > -1e6 && umax < 1e6 && wmin > -1e6 && wmax < 1e6) {
+                b.x0 = static_cast<int>(floor(umin - 1e-6));
+                b.y0 = static_cast<int>(floor(wmin - 1e-6));
+                b.w = static_cast<int>(floor(umax + 1e-6)) + 2 - b.x0;
+                b.h = static_cast<int>(floor(wmax + 1e-6)) + 2 - b.y0;
+                // sides are checked before the product so it cannot overflow
+                b.ok = (b.w > 0 && b.h > 0 && b.w <= kBoxCap && b.h <= kBoxCap && b.w * b.h <= kBoxCap) ? 1 : 0;
+            }
+            boxes[v] = b;
+        }
+    }
+}
+
+__device__ __forceinline__ PixBox read_box(const PixBox *boxes, int v)
+{
+    PixBox b;
+    b.x0 = __builtin_amdgcn_readfirstlane(boxes[v].x0);
+    b.y0 = __builtin_amdgcn_readfirstlane(boxes[v].y0);
+    b.w = __builtin_amdgcn_readfirstlane(boxes[v].w);
+    b.h = __builtin_amdgcn_readfirstlane(boxes[v].h);
+    b.ok = __builtin_amdgcn_readfirstlane(boxes[v].ok);
+    return b;
+}
+
+// Element e of a box, row-major: r = e / w without an integer division
+// ((e + 1/2) / w is at least 1/(2w) away from an integer for e < 2^22).
+__device__ __forceinline__ void box_rc(int e, int w, float inv_w, int &r, int &c)
+{
+    r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_w);
+    c = e - r * w;
+}
+
+// Copies a view's map over the box into LDS; pixels outside the image read as
+// 0. All loads of a lane are issued before its LDS stores.
+__device__ __forceinline__ void stage_box(float *lds, const PixBox &b, const float *map, int W, int H)
+{
+    const int area = b.w * b.h;
+    const float inv_w = 1.0f / static_cast<float>(b.w);
+    float vals[kStageIters];
+#pragma unroll
+    for (int t = 0; t < kStageIters; ++t) {
+        const int e = static_cast<int>(threadIdx.x) + t * kBlock;
+        vals[t] = 0.0f;
+        if (e < area) {
+            int r, c;
+            box_rc(e, b.w, inv_w, r, c);
+            const int x = b.x0 + c, y = b.y0 + r;
+            if (x >= 0 && x < W && y >= 0 && y < H) vals[t] = map[static_cast<int64_t>(y) * W + x];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kStageIters; ++t) {
+        const int e = static_cast<int>(threadIdx.x) + t * kBlock;
+        if (e < area) lds[e] = vals[t];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
 {
+    __shared__ float lmap_box[kBoxCap];
+    __shared__ PixBox boxes[kMaxViews];
     const Coords q = block_coords<kFwdKZ>(a.nx, a.ny, a.nz);
+    compute_boxes<kFwdKZ>(a, q, boxes);
     const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (q.i + 0.5);
     const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (q.j + 0.5);
     float L[kFwdKZ];
 #pragma unroll
     for (int kk = 0; kk < kFwdKZ; ++kk) L[kk] = a.L0;
+    __syncthreads();
 
     for (int v = 0; v < a.n; ++v) {
         const ViewGeom &g = a.view[v];
         const float *map = a.lmap + g.map_off;
         const Proj64 p = proj64_column(g, Xd, Yd);
+        const PixBox box = read_box(boxes, v);
+        if (box.ok) {
+            __syncthreads();                // the previous view's reads are done
+            stage_box(lmap_box, box, map, g.W, g.H);
+            __syncthreads();
+        }
 #pragma unroll
         for (int kk = 0; kk < kFwdKZ; ++kk) {
-            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.k0 + kk + 0.5);
+            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
             Tap4 t;
-            if (project64(p, Zd, t)) L[kk] += bilinear_sample(map, g.W, g.H, t.x0, t.y0, t.fx, t.fy);
+            if (!project64(p, Zd, t)) continue;
+            const int lx = static_cast<int>(t.x0) - box.x0, ly = static_cast<int>(t.y0) - box.y0;
+            if (box.ok && t.x0 >= box.x0 && t.y0 >= box.y0 && lx + 1 < box.w && ly + 1 < box.h) {
+                const float *s = lmap_box + ly * box.w + lx;
+                const float top = fmaf(t.fx, s[1] - s[0], s[0]);
+                const float bot = fmaf(t.fx, s[box.w + 1] - s[box.w], s[box.w]);
+                L[kk] += fmaf(t.fy, bot - top, top);
+            } else {
+                L[kk] += bilinear_sample(map, g.W, g.H, t.x0, t.y0, t.fx, t.fy);
+            }
         }
     }
 
@@ -125,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
     if (q.i < a.nx && q.j < a.ny) {
 #pragma unroll
         for (int kk = 0; kk < kFwdKZ; ++kk) {
-            const int k = q.k0 + kk;
+            const int k = q.kb + q.lz + 4 * kk;
             if (k >= a.nz) continue;
             const int64_t idx = (static_cast<int64_t>(k) * a.ny + q.j) * a.nx + q.i;
             a.logits[idx] = L[kk];
@@ -170,49 +343,82 @@ __global__ __launch_bounds__(256) void zero_kernel(float *p, int64_t n4)
 
 __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
 {
+    __shared__ float lmap_box[kBoxCap];
+    __shared__ int adj_box[kBoxCap];
+    __shared__ float cam[kWaves][kMaxViews * 12];
+    __shared__ PixBox boxes[kMaxViews];
     const Coords q = block_coords<kBwdKZ>(a.nx, a.ny, a.nz);
     const float X = a.ox + a.h * (static_cast<float>(q.i) + 0.5f);
     const float Y = a.oy + a.h * (static_cast<float>(q.j) + 0.5f);
     const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (q.i + 0.5);
     const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (q.j + 0.5);
     const float gl = *a.grad_loss;
+    const float qscale = ldexpf(1.0f, adjoint_exponent(gl, a.inv_count));
 
     float gv[kBwdKZ];
+    bool any = false;
 #pragma unroll
     for (int kk = 0; kk < kBwdKZ; ++kk) {
-        const int k = q.k0 + kk;
+        const int k = q.kb + q.lz + 4 * kk;
         gv[kk] = 0.0f;
         if (q.i < a.nx && q.j < a.ny && k < a.nz && in_region(a, q.i, q.j, k)) {
             const int64_t idx = (static_cast<int64_t>(k) * a.ny + q.j) * a.nx + q.i;
             gv[kk] = gl * (sigmoidf_stable(a.logits[idx]) - static_cast<float>(a.labels[idx])) * a.inv_count;
+            any = any || gv[kk] != 0.0f;
         }
     }
-
-    __shared__ float cam[kWaves][kMaxViews * 12];
+    // a workgroup with no voxel in the loss region contributes nothing
+    const bool block_any = __syncthreads_or(any ? 1 : 0) != 0;
+    if (block_any) compute_boxes<kBwdKZ>(a, q, boxes);
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
     for (int v = 0; v < a.n; ++v) {
         const ViewGeom &g = a.view[v];
         const float *map = a.lmap + g.map_off;
-        float *adj = a.adj + g.map_off;
+        unsigned long long *adj = reinterpret_cast<unsigned long long *>(a.adj) + g.map_off;
         const Proj64 p = proj64_column(g, Xd, Yd);
+        PixBox box{0, 0, 0, 0, 0};
+        if (block_any) box = read_box(boxes, v);
+        if (box.ok) {
+            __syncthreads();                // the previous view's flush is done
+            stage_box(lmap_box, box, map, g.W, g.H);
+            for (int e = threadIdx.x; e < box.w * box.h; e += kBlock) adj_box[e] = 0;
+            __syncthreads();
+        }
         float su = 0.0f, suz = 0.0f, sv = 0.0f, svz = 0.0f, sc = 0.0f, scz = 0.0f;
 #pragma unroll
         for (int kk = 0; kk < kBwdKZ; ++kk) {
             if (gv[kk] == 0.0f) continue;
-            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.k0 + kk + 0.5);
+            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
             Tap4 t;
             if (!project64(p, Zd, t)) continue;
             if (!(t.x0 >= -1.0 && t.x0 < g.W && t.y0 >= -1.0 && t.y0 < g.H)) continue;
             const int ix = static_cast<int>(t.x0), iy = static_cast<int>(t.y0);
             const bool xin0 = ix >= 0, xin1 = ix + 1 < g.W, yin0 = iy >= 0, yin1 = iy + 1 < g.H;
-            const int64_t base = static_cast<int64_t>(iy) * g.W + ix;
             const float fx = t.fx, fy = t.fy, gk = gv[kk];
-            float l00 = 0.0f, l10 = 0.0f, l01 = 0.0f, l11 = 0.0f;
-            if (xin0 && yin0) { l00 = map[base]; unsafeAtomicAdd(adj + base, gk * (1.0f - fx) * (1.0f - fy)); }
-            if (xin1 && yin0) { l10 = map[base + 1]; unsafeAtomicAdd(adj + base + 1, gk * fx * (1.0f - fy)); }
-            if (xin0 && yin1) { l01 = map[base + g.W]; unsafeAtomicAdd(adj + base + g.W, gk * (1.0f - fx) * fy); }
-            if (xin1 && yin1) { l11 = map[base + g.W + 1]; unsafeAtomicAdd(adj + base + g.W + 1, gk * fx * fy); }
+            const int q00 = static_cast<int>(rintf(gk * (1.0f - fx) * (1.0f - fy) * qscale));
+            const int q10 = static_cast<int>(rintf(gk * fx * (1.0f - fy) * qscale));
+            const int q01 = static_cast<int>(rintf(gk * (1.0f - fx) * fy * qscale));
+            const int q11 = static_cast<int>(rintf(gk * fx * fy * qscale));
+            float l00, l10, l01, l11;
+            const int lx = ix - box.x0, ly = iy - box.y0;
+            if (box.ok && lx >= 0 && ly >= 0 && lx + 1 < box.w && ly + 1 < box.h) {
+                // out-of-image taps of the box hold 0 and are never flushed
+                const int e = ly * box.w + lx;
+                l00 = lmap_box[e]; l10 = lmap_box[e + 1]; l01 = lmap_box[e + box.w]; l11 = lmap_box[e + box.w + 1];
+                atomicAdd(&adj_box[e], q00);
+                atomicAdd(&adj_box[e + 1], q10);
+                atomicAdd(&adj_box[e + box.w], q01);
+                atomicAdd(&adj_box[e + box.w + 1], q11);
+            } else {
+                const int64_t base = static_cast<int64_t>(iy) * g.W + ix;
+                l00 = l10 = l01 = l11 = 0.0f;
+                if (xin0 && yin0) { l00 = map[base]; atomicAdd(adj + base, widen(q00)); }
+                if (xin1 && yin0) { l10 = map[base + 1]; atomicAdd(adj + base + 1, widen(q10)); }
+                if (xin0 && yin1) { l01 = map[base + g.W]; atomicAdd(adj + base + g.W, widen(q01)); }
+                if (xin1 && yin1) { l11 = map[base + g.W + 1]; atomicAdd(adj + base + g.W + 1, widen(q11)); }
+            }
             const float dldu = (1.0f - fy) * (l10 - l00) + fy * (l11 - l01);
             const float dldv = (1.0f - fx) * (l01 - l00) + fx * (l11 - l10);
             const float gu = gk * dldu * t.rc, gw = gk * dldv * t.rc;
@@ -222,12 +428,29 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
             sv += gw; svz = fmaf(gw, Z, svz);
             sc += gc; scz = fmaf(gc, Z, scz);
         }
+        if (box.ok) {
+            __syncthreads();                // every scatter into the box is done
+            const int area = box.w * box.h;
+            const float inv_w = 1.0f / static_cast<float>(box.w);
+            for (int e = threadIdx.x; e < area; e += kBlock) {
+                int r, c;
+                box_rc(e, box.w, inv_w, r, c);
+                const int x = box.x0 + c, y = box.y0 + r;
+                const int val = adj_box[e];
+                if (x >= 0 && x < g.W && y >= 0 && y < g.H && val != 0)
+                    atomicAdd(adj + static_cast<int64_t>(y) * g.W + x, widen(val));
+            }
+        }
         // dLoss/dP row r = sum over the lane's voxels of g_r * (X, Y, Z, 1)
-        const float vals[12] = {X * su, Y * su, suz, su, X * sv, Y * sv, svz, sv, X * sc, Y * sc, scz, sc};
+        if (block_any) {
+            const float vals[12] = {X * su, Y * su, suz, su, X * sv, Y * sv, svz, sv, X * sc, Y * sc, scz, sc};
 #pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            const float r = wave_sum(vals[e]);
-            if (lane == 0) cam[wave][v * 12 + e] = r;
+            for (int e = 0; e < 12; ++e) {
+                const float r = wave_total(vals[e]);
+                if (lane == 0) cam[wave][v * 12 + e] = r;
+            }
+        } else if (lane < 12) {
+            cam[wave][v * 12 + lane] = 0.0f;
         }
     }
     __syncthreads();
@@ -274,13 +497,16 @@ __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
     const ChainView cv = a.view[blockIdx.y];
     const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
     if (p0 >= cv.npix) return;
-    const float *A = a.adj + cv.map_off + p0;
+    const long long *Aq = reinterpret_cast<const long long *>(a.adj) + cv.map_off + p0;
+    const double unit = ldexp(1.0, -adjoint_exponent(*a.grad_loss, a.inv_count));
+    float A[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) A[t] = p0 + t < cv.npix ? static_cast<float>(static_cast<double>(Aq[t]) * unit) : 0.0f;
     if (p0 + 4 <= cv.npix) {
         const uint32_t *iw = reinterpret_cast<const uint32_t *>(cv.img + 3 * p0);
         const uint32_t w[3] = {iw[0], iw[1], iw[2]};
         const f32x4 *mp = reinterpret_cast<const f32x4 *>(cv.mean + 3 * p0);
         const f32x4 *vp = reinterpret_cast<const f32x4 *>(cv.var + 3 * p0);
-        const f32x4 A4 = *reinterpret_cast<const f32x4 *>(A);
         float m[12], v[12], gm[12], gvv[12];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -288,11 +514,10 @@ __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
             m[4 * r] = mm.x; m[4 * r + 1] = mm.y; m[4 * r + 2] = mm.z; m[4 * r + 3] = mm.w;
             v[4 * r] = vv.x; v[4 * r + 1] = vv.y; v[4 * r + 2] = vv.z; v[4 * r + 3] = vv.w;
         }
-        const float Av[4] = {A4.x, A4.y, A4.z, A4.w};
 #pragma unroll
         for (int px = 0; px < 4; ++px) {
             const int b = 3 * px;
-            chain_pixel(Av[px], byte_of(w[b / 4], b % 4), byte_of(w[(b + 1) / 4], (b + 1) % 4),
+            chain_pixel(A[px], byte_of(w[b / 4], b % 4), byte_of(w[(b + 1) / 4], (b + 1) % 4),
                         byte_of(w[(b + 2) / 4], (b + 2) % 4), m + b, v + b, a.k0, gm + b, gvv + b);
         }
         f32x4 *gmo = reinterpret_cast<f32x4 *>(cv.gmean + 3 * p0);
@@ -313,7 +538,7 @@ __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
 
 int64_t nblocks(int nx, int ny, int nz, int kz)
 {
-    return static_cast<int64_t>((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY) * ((nz + kz - 1) / kz);
+    return static_cast<int64_t>((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + 4 * kz - 1) / (4 * kz));
 }
 
 }  // namespace

@@ -60,7 +60,7 @@ struct FuseArgs {
 struct DiffArgs {
     ViewGeom view[kMaxViews];
     const float *lmap;                  // log(2*SLM) maps
-    float *adj;                         // adjoint maps dLoss/dlog(2*SLM), same layout
+    float *adj;                         // adjoint maps dLoss/dlog(2*SLM), int64 fixed point, same element layout
     const uint8_t *labels;              // [nz][ny][nx] 0/1
     float *logits;                      // [nz][ny][nx]
     const float *grad_loss;             // device scalar (backward)
@@ -86,7 +86,9 @@ struct ChainView {
 
 struct ChainArgs {
     ChainView view[kMaxViews];
-    const float *adj;
+    const float *adj;                   // int64 fixed-point adjoint maps (see diff.hip)
+    const float *grad_loss;
+    float inv_count;
     float k0;
     int32_t n;
 };
