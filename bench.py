@@ -1,11 +1,14 @@
 """Benchmark of the occupancy pass on one MI355X.
 
-A step reconstructs one frame of the 128^3-voxel, 8-view, 640x480 workload:
-likelihood maps of all views (Eq. 1-2), then projection + gather + fusion +
-posterior + threshold of every voxel (Eq. 3-9). Inputs are resident in HBM
-before the timed region; frames rotate over several independent slots (each
-with its own images and background model) so the working set exceeds the
-256 MB Infinity Cache and every step streams its inputs from HBM.
+A step reconstructs one frame of the 128^3-voxel, 8-view, 640x480 workload
+within a frame sequence: one launch computes the likelihood maps of all views
+of frame t+1 (Eq. 1-2) beside the projection + gather + fusion + posterior +
+threshold of every voxel of frame t (Eq. 3-9), from the maps the previous
+launch wrote. Inputs are resident in HBM before the timed region; frames
+rotate over several independent slots (each with its own images and
+background model) so the working set exceeds the 256 MB Infinity Cache and
+every step streams its inputs from HBM. The two-launch single-frame path
+(likelihood, then fusion) is timed beside it.
 
 Prints one JSON line (the contract of the driver) with the headline value,
 the dominant kernel's roofline figure and the FP64 CPU oracle's rate.
@@ -90,7 +93,16 @@ def main():
         slots.append(dict(plan=plan, ims=ims, mus=mus, vs=vs, post=post, occ=occ, ws=ws))
     torch.cuda.synchronize()
 
+    maps = [slots[0]["plan"].new_lmap(), slots[0]["plan"].new_lmap()]
+    assert len(slots) % 2 == 0, "an even slot count keeps the two map buffers in step with the cycle"
+
     def step(i):
+        # maps of frame i+1 into one buffer, fusion of frame i from the other;
+        # every slot has the same rig and grid, so slot i+1's plan fuses frame i
+        s, nx = slots[i % len(slots)], slots[(i + 1) % len(slots)]
+        nx["plan"].pipeline_step(nx["ims"], maps[(i + 1) % 2], maps[i % 2], s["post"], s["occ"])
+
+    def single(i):
         s = slots[i % len(slots)]
         s["plan"].reconstruct(s["ims"], s["post"], s["occ"], s["ws"])
 
@@ -162,16 +174,26 @@ def main():
     graph = not args.eager
     steps = (args.steps // len(slots)) * len(slots) if graph else args.steps
     steps = max(steps, len(slots))
+    with torch.cuda.stream(stream):
+        step(len(slots) - 1)                  # maps of frame 0 for the first timed step
     ms, done = timed(step, steps, args.warmup, graph)
-    print(f"[bench] {done} steps, {ms * 1e3:.2f} us/step", file=sys.stderr, flush=True)
-    ms_l, _ = timed(only_lmap, steps, args.warmup, graph)
-    ms_f, _ = timed(only_fuse, steps, args.warmup, graph)
-    print(f"[bench] likelihood {ms_l * 1e3:.2f} us, fusion {ms_f * 1e3:.2f} us", file=sys.stderr, flush=True)
+    print(f"[bench] {done} pipelined steps, {ms * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    ms_single, _ = timed(single, steps, args.warmup, graph)
+    print(f"[bench] single-frame path (two launches) {ms_single * 1e3:.2f} us/frame", file=sys.stderr, flush=True)
+    # per-launch durations: HIP events on the launch stream around each launch
+    ev_n = min(steps, 240)
+    us_pipe = launch_us(torch, stream, step, ev_n)
+    us_l = launch_us(torch, stream, only_lmap, ev_n)
+    us_f = launch_us(torch, stream, only_fuse, ev_n)
+    print(f"[bench] per launch: pipe {us_pipe:.2f} us, likelihood {us_l:.2f} us, fusion {us_f:.2f} us",
+          file=sys.stderr, flush=True)
 
     # parity spot check of the timed configuration on sampled voxels
     from oracle import oracle as O
     s0 = slots[0]
-    step(0)
+    with torch.cuda.stream(stream):
+        step(len(slots) - 1)
+        step(0)
     torch.cuda.synchronize()
     maps = [O.slm(i, m, v) for i, m, v in zip(fr0.images, fr0.mean, fr0.var)]
     ref = O.posterior(fr0.cams, fr0.grid, maps)
@@ -179,14 +201,12 @@ def main():
     un = ref.ncombo == 1
     max_err = float(np.abs(got - ref.post)[un].max())
 
-    # roofline of the dominant kernel: algorithmic HBM bytes per launch
-    bytes_lmap = 27 * npix + 4 * npix              # image+mean+var read, map written
-    bytes_fuse = 4 * npix + 5 * V                  # map read once, posterior+occupancy written
-    if ms_l >= ms_f:
-        dom, dom_ms, dom_bytes = "slm_kernel", ms_l, bytes_lmap
-    else:
-        dom, dom_ms, dom_bytes = "fuse_kernel", ms_f, bytes_fuse
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    # roofline of the step's one kernel: algorithmic HBM bytes per launch are
+    # the frame's inputs (image + mean + variance, 27 B/pixel) and outputs
+    # (posterior + occupancy, 5 B/voxel); the maps are an intermediate
+    step_bytes = 27 * npix + 5 * V
+    dom, dom_us, dom_bytes = "pipe_kernel", us_pipe, step_bytes
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
 
     diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
@@ -221,23 +241,41 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "psfs-forward: 128^3 voxel grid over 2 m, 8 ring views 640x480 f=600, "
-                               "10-ellipsoid body, per-pixel Gaussian background",
+                               "10-ellipsoid body, per-pixel Gaussian background; frame sequence, one launch "
+                               "per frame (maps of frame t+1 beside fusion of frame t)",
                    "frames_per_step": 1, "slots": len(slots), "graph": graph,
                    "voxels": V, "views": n, "pixels": npix},
         "frames_per_s": 1e3 / ms,
-        "kernels_us": {"slm_kernel": ms_l * 1e3, "fuse_kernel": ms_f * 1e3},
+        "single_frame_path_us": ms_single * 1e3,
+        "kernels_us": {"pipe_kernel": us_pipe, "slm_kernel": us_l, "fuse_kernel": us_f},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": dom_bytes},
-        "step_roofline": {"algorithmic_bytes": 27 * npix + 5 * V,
-                          "achieved_GBs": (27 * npix + 5 * V) / (ms * 1e-3) / 1e9,
-                          "frac": (27 * npix + 5 * V) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "step_roofline": {"algorithmic_bytes": step_bytes,
+                          "achieved_GBs": step_bytes / (ms * 1e-3) / 1e9,
+                          "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "parity_max_abs_err": max_err,
         "fwd_bwd": diff,
         "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def launch_us(torch, stream, fn, count):
+    """Mean duration of one launch of fn (microseconds): a pair of HIP events
+    recorded on the launch stream around every launch, eager launches."""
+    with torch.cuda.stream(stream):
+        for i in range(6):
+            fn(i)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+        for i, (a, b) in enumerate(ev):
+            a.record(stream)
+            fn(i)
+            b.record(stream)
+        torch.cuda.synchronize()
+    return 1e3 * sum(a.elapsed_time(b) for a, b in ev) / count
 
 
 def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):

@@ -146,6 +146,28 @@ int psfs_fuse(psfs_plan *plan, const float *lmap_dev, float *posterior_dev, uint
 int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev,
                      uint8_t *occ_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* One step of a frame sequence seen by one rig, as one launch: the
+ * likelihood maps of the next frame (Eq. 1-2, as psfs_likelihood of
+ * images_dev into lmap_next_dev) and the fusion of the current frame (Eq. 3-9,
+ * as psfs_fuse of lmap_cur_dev into posterior_dev / occ_dev), the two parts
+ * running side by side on the GPU. Frame t's maps come from step t-1, so with
+ * two map buffers used in turn a sequence costs one launch per frame (the
+ * paper overlaps transfers, CPU work and kernels through several command
+ * queues, Sec. 3.3.2; here the overlap is inside one launch).
+ *   images_dev      n device pointers of the next frame, or NULL: no
+ *                   likelihood part (backgrounds must be set otherwise)
+ *   lmap_next_dev   psfs_lmap_floats floats, 16-byte aligned (unused if
+ *                   images_dev is NULL)
+ *   lmap_cur_dev    maps of the current frame in the same layout, written by
+ *                   an earlier call; must not overlap lmap_next_dev
+ *   posterior_dev   FP32 [nz][ny][nx] of the current frame, or NULL: no fusion
+ *                   part (then occ_dev must be NULL too)
+ *   occ_dev         nullable u8 [nz][ny][nx]
+ * Results are bit-identical to psfs_likelihood and psfs_fuse. Both parts NULL
+ * is a no-op. Cameras and grid must be set (PSFS_E_NOT_READY). */
+int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap_next_dev,
+                       const float *lmap_cur_dev, float *posterior_dev, uint8_t *occ_dev, void *stream);
+
 /* occ[i] = posterior[i] > tau for i < nvox (Sec. 2.2.2 thresholding);
  * tau in [0,1]; nvox >= 0. */
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,

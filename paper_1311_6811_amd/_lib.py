@@ -69,6 +69,7 @@ SIGNATURES = {
     "psfs_likelihood": (C.c_int, [vp, C.POINTER(vp), vp, vp]),
     "psfs_fuse": (C.c_int, [vp, vp, vp, vp, vp]),
     "psfs_reconstruct": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
+    "psfs_pipeline_step": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, vp, vp]),
     "psfs_threshold": (C.c_int, [vp, C.c_int64, C.c_float, vp, vp]),
     "psfs_diff_workspace_bytes": (C.c_size_t, [vp]),
     "psfs_diff_forward": (C.c_int, [vp, C.POINTER(vp), vp, i32p, vp, vp, vp, C.c_size_t, vp]),

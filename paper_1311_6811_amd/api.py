@@ -187,6 +187,24 @@ class Plan:
                                          ws.numel(), _stream()))
         return post, occ
 
+    def new_lmap(self) -> torch.Tensor:
+        return torch.empty(max(self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
+
+    def pipeline_step(self, images=None, lmap_next: Optional[torch.Tensor] = None,
+                      lmap_cur: Optional[torch.Tensor] = None, posterior=None, occ=None) -> None:
+        """One launch: likelihood maps of `images` into `lmap_next` and fusion of
+        the maps `lmap_cur` (from an earlier step) into `posterior` / `occ`.
+        Either part may be omitted (images=None / posterior=None)."""
+        ims = self._images(images) if images is not None else None
+        nxt = _dev(lmap_next, torch.float32, "lmap_next") if images is not None else None
+        cur = pp = op = None
+        if posterior is not None:
+            shape = (self.grid.nz, self.grid.ny, self.grid.nx)
+            pp = _dev(posterior, torch.float32, "posterior", shape)
+            op = _dev(occ, torch.uint8, "occ", shape) if occ is not None else None
+            cur = _dev(lmap_cur, torch.float32, "lmap_cur")
+        L.check(L.lib().psfs_pipeline_step(self._h, ims, nxt, cur, pp, op, _stream()))
+
     # ------------------------------------------- differentiable variant
     def diff_workspace_bytes(self) -> int:
         return int(L.lib().psfs_diff_workspace_bytes(self._h))
@@ -237,6 +255,52 @@ class Plan:
                                            workspace.numel(), _stream()))
         self._keep["grad_loss"] = gl
         return gmeans, gvars, gP[: self.n]
+
+
+class Pipeline:
+    """Frame sequence from one rig with one launch per frame: push(frame t+1)
+    fuses frame t (pushed before) while computing the maps of frame t+1.
+
+        pipe = Pipeline(plan)
+        for images in frames:
+            out = pipe.push(images)       # outputs of the previous frame, or None
+        out = pipe.flush()                # outputs of the last frame
+    """
+
+    def __init__(self, plan: Plan, want_occ: bool = True):
+        self.plan = plan
+        self.want_occ = want_occ
+        self._maps = [plan.new_lmap(), plan.new_lmap()]
+        self._cur = -1                       # map buffer holding the pending frame
+
+    def _outputs(self):
+        g = self.plan.grid
+        shape = (g.nz, g.ny, g.nx)
+        post = torch.empty(shape, dtype=torch.float32, device="cuda")
+        occ = torch.empty(shape, dtype=torch.uint8, device="cuda") if self.want_occ else None
+        return post, occ
+
+    def push(self, images, posterior=None, occ=None):
+        nxt = 0 if self._cur != 0 else 1
+        out = None
+        if self._cur >= 0:
+            if posterior is None:
+                posterior, occ = self._outputs()
+            out = (posterior, occ)
+            self.plan.pipeline_step(images, self._maps[nxt], self._maps[self._cur], posterior, occ)
+        else:
+            self.plan.pipeline_step(images, self._maps[nxt])
+        self._cur = nxt
+        return out
+
+    def flush(self, posterior=None, occ=None):
+        if self._cur < 0:
+            return None
+        if posterior is None:
+            posterior, occ = self._outputs()
+        self.plan.pipeline_step(None, None, self._maps[self._cur], posterior, occ)
+        self._cur = -1
+        return posterior, occ
 
 
 class BatchFrame:

@@ -144,12 +144,10 @@ int check_images(const psfs_plan *p, const uint8_t *const *images)
     return PSFS_OK;
 }
 
-int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *lmap, hipStream_t s)
+// Likelihood-kernel arguments for the views of p; returns the largest view's
+// pixel count.
+int64_t fill_slm(const psfs_plan *p, const uint8_t *const *images, float *lmap, SlmArgs &a)
 {
-    if (p->n == 0) return PSFS_OK;
-    int rc = check_device();
-    if (rc) return rc;
-    SlmArgs a{};
     a.n = p->n;
     a.lmap = lmap;
     a.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(p->params.log_u));
@@ -159,6 +157,16 @@ int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *
         a.view[k] = SlmView{images[k], p->mean[k], p->var[k], np, map_offset(p, k)};
         if (np > max_np) max_np = np;
     }
+    return max_np;
+}
+
+int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *lmap, hipStream_t s)
+{
+    if (p->n == 0) return PSFS_OK;
+    int rc = check_device();
+    if (rc) return rc;
+    SlmArgs a{};
+    const int64_t max_np = fill_slm(p, images, lmap, a);
     hipError_t e = launch_slm(a, max_np, s);
     if (e != hipSuccess) return hip_fail(e, "likelihood kernel launch");
     return PSFS_OK;
@@ -440,6 +448,49 @@ int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *p
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = enqueue_likelihood(plan, images_dev, lmap, s))) return rc;
     return enqueue_fuse(plan, lmap, posterior_dev, occ_dev, s);
+    PSFS_GUARD_END
+}
+
+int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap_next_dev,
+                       const float *lmap_cur_dev, float *posterior_dev, uint8_t *occ_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_grid(plan);
+    if (rc) return rc;
+    const bool next = images_dev != nullptr, cur = posterior_dev != nullptr;
+    const int64_t maps = map_floats(plan);
+    if (next) {
+        if ((rc = need_backgrounds(plan))) return rc;
+        if ((rc = check_images(plan, images_dev))) return rc;
+        if (plan->n > 0 && (!lmap_next_dev || !aligned(lmap_next_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap_next must be a 16-byte aligned device pointer");
+    }
+    if (cur) {
+        if (!aligned(posterior_dev, 16)) return fail(PSFS_E_ARG, "posterior must be 16-byte aligned");
+        if (plan->n > 0 && (!lmap_cur_dev || !aligned(lmap_cur_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap_cur must be a 16-byte aligned device pointer");
+    } else if (occ_dev) {
+        return fail(PSFS_E_ARG, "occupancy given without a posterior");
+    }
+    if (next && cur && maps > 0) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(lmap_next_dev), b0 = reinterpret_cast<uintptr_t>(lmap_cur_dev);
+        const uintptr_t len = static_cast<uintptr_t>(maps) * sizeof(float);
+        if (a0 < b0 + len && b0 < a0 + len) return fail(PSFS_E_ARG, "lmap_next and lmap_cur overlap");
+    }
+    SlmArgs sa{};
+    int64_t max_np = 0;
+    if (next && plan->n > 0) max_np = fill_slm(plan, images_dev, lmap_next_dev, sa);
+    FuseArgs fa{};
+    fill_geometry(plan, plan->params.sampling, fa);
+    fa.lmap = lmap_cur_dev;
+    fa.post = (cur && nvox(plan->grid) > 0) ? posterior_dev : nullptr;
+    fa.occ = fa.post ? occ_dev : nullptr;
+    if (sa.n == 0 && !fa.post) return PSFS_OK;
+    if ((rc = check_device())) return rc;
+    const int tile = plan->tile >= 0 ? plan->tile : default_tile();
+    hipError_t e = launch_pipeline(sa, fa, tile, plan->params.sampling, max_np, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pipelined kernel launch");
+    return PSFS_OK;
     PSFS_GUARD_END
 }
 

@@ -17,7 +17,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int kChunkPixels = 1024;      // 256 lanes x 4 pixels
+constexpr int kChunkPixels = 4 * kWavePixels;   // one per wave of a workgroup
 constexpr int kGroup = 4;               // items popped per atomic
 
 __device__ __forceinline__ int find_view(const BatchView *views, int nviews, int64_t chunk)
@@ -51,40 +51,10 @@ __device__ __forceinline__ int64_t pop(unsigned long long *counter)
     return r;
 }
 
-__device__ __forceinline__ void slm_quad(const BatchView &bv, float *lmap, float k0, int64_t p0)
-{
-    if (p0 >= bv.npix) return;
-    float *out = lmap + bv.g.map_off + p0;
-    if (p0 + 4 <= bv.npix) {
-        const uint32_t *iw = reinterpret_cast<const uint32_t *>(bv.img + 3 * p0);
-        const uint32_t w0 = __builtin_nontemporal_load(iw + 0);
-        const uint32_t w1 = __builtin_nontemporal_load(iw + 1);
-        const uint32_t w2 = __builtin_nontemporal_load(iw + 2);
-        const f32x4 *mp = reinterpret_cast<const f32x4 *>(bv.mean + 3 * p0);
-        const f32x4 *vp = reinterpret_cast<const f32x4 *>(bv.var + 3 * p0);
-        const f32x4 m0 = __builtin_nontemporal_load(mp + 0);
-        const f32x4 m1 = __builtin_nontemporal_load(mp + 1);
-        const f32x4 m2 = __builtin_nontemporal_load(mp + 2);
-        const f32x4 v0 = __builtin_nontemporal_load(vp + 0);
-        const f32x4 v1 = __builtin_nontemporal_load(vp + 1);
-        const f32x4 v2 = __builtin_nontemporal_load(vp + 2);
-        f32x4 r;
-        r.x = log2slm(byte_of(w0, 0), byte_of(w0, 1), byte_of(w0, 2), m0.x, m0.y, m0.z, v0.x, v0.y, v0.z, k0);
-        r.y = log2slm(byte_of(w0, 3), byte_of(w1, 0), byte_of(w1, 1), m0.w, m1.x, m1.y, v0.w, v1.x, v1.y, k0);
-        r.z = log2slm(byte_of(w1, 2), byte_of(w1, 3), byte_of(w2, 0), m1.z, m1.w, m2.x, v1.z, v1.w, v2.x, k0);
-        r.w = log2slm(byte_of(w2, 1), byte_of(w2, 2), byte_of(w2, 3), m2.y, m2.z, m2.w, v2.y, v2.z, v2.w, k0);
-        *reinterpret_cast<f32x4 *>(out) = r;
-    } else {
-        for (int64_t p = p0; p < bv.npix; ++p) {
-            const uint8_t *I = bv.img + 3 * p;
-            const float *m = bv.mean + 3 * p, *v = bv.var + 3 * p;
-            out[p - p0] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], k0);
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void batch_slm_kernel(BatchArgs a)
 {
+    __shared__ SlmStage stage[4];
+    const int wave = static_cast<int>(threadIdx.x >> 6);
     for (;;) {
         const int64_t c0 = pop(a.counters + 0);
         if (c0 >= a.nchunks) break;
@@ -92,7 +62,12 @@ __global__ __launch_bounds__(256) void batch_slm_kernel(BatchArgs a)
         for (int64_t c = c0; c < c1; ++c) {
             const int v = __builtin_amdgcn_readfirstlane(find_view(a.views, a.nviews, c));
             const BatchView &bv = a.views[v];
-            slm_quad(bv, a.lmap, a.k0, (c - bv.chunk0) * kChunkPixels + static_cast<int64_t>(threadIdx.x) * 4);
+            const int64_t p0 = (c - bv.chunk0) * kChunkPixels + wave * kWavePixels;
+            float *out = a.lmap + bv.g.map_off;
+            if (p0 + kWavePixels <= bv.npix)
+                slm_wave(bv.img, bv.mean, bv.var, out, p0, a.k0, stage[wave]);
+            else if (p0 < bv.npix)
+                slm_wave_tail(bv.img, bv.mean, bv.var, out, p0, bv.npix, a.k0);
         }
     }
 }

@@ -16,85 +16,30 @@ namespace {
 
 using namespace dev;
 
-constexpr int kSlmQuads = 2;            // pixel quads per lane in slm_kernel
-
-struct Quad {
-    uint32_t w[3];
-    f32x4 m[3], v[3];
-};
-
-__device__ __forceinline__ void load_quad(const SlmView &sv, int64_t p0, Quad &q)
-{
-    const uint32_t *iw = reinterpret_cast<const uint32_t *>(sv.img + 3 * p0);
-    const f32x4 *mp = reinterpret_cast<const f32x4 *>(sv.mean + 3 * p0);
-    const f32x4 *vp = reinterpret_cast<const f32x4 *>(sv.var + 3 * p0);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        q.w[r] = __builtin_nontemporal_load(iw + r);
-        q.m[r] = __builtin_nontemporal_load(mp + r);
-        q.v[r] = __builtin_nontemporal_load(vp + r);
-    }
-}
-
-__device__ __forceinline__ f32x4 quad_log2slm(const Quad &q, float k0)
-{
-    f32x4 r;
-    r.x = log2slm(byte_of(q.w[0], 0), byte_of(q.w[0], 1), byte_of(q.w[0], 2), q.m[0].x, q.m[0].y, q.m[0].z,
-                  q.v[0].x, q.v[0].y, q.v[0].z, k0);
-    r.y = log2slm(byte_of(q.w[0], 3), byte_of(q.w[1], 0), byte_of(q.w[1], 1), q.m[0].w, q.m[1].x, q.m[1].y,
-                  q.v[0].w, q.v[1].x, q.v[1].y, k0);
-    r.z = log2slm(byte_of(q.w[1], 2), byte_of(q.w[1], 3), byte_of(q.w[2], 0), q.m[1].z, q.m[1].w, q.m[2].x,
-                  q.v[1].z, q.v[1].w, q.v[2].x, k0);
-    r.w = log2slm(byte_of(q.w[2], 1), byte_of(q.w[2], 2), byte_of(q.w[2], 3), q.m[2].y, q.m[2].z, q.m[2].w,
-                  q.v[2].y, q.v[2].z, q.v[2].w, k0);
-    return r;
-}
-
-__device__ __forceinline__ void tail_pixels(const SlmView &sv, float *lmap, float k0, int64_t p0)
-{
-    for (int64_t p = p0; p < sv.npix; ++p) {
-        const uint8_t *I = sv.img + 3 * p;
-        const float *m = sv.mean + 3 * p, *v = sv.var + 3 * p;
-        lmap[sv.map_off + p] = log2slm(I[0], I[1], I[2], m[0], m[1], m[2], v[0], v[1], v[2], k0);
-    }
-}
-
-// A lane converts kSlmQuads groups of 4 consecutive pixels, kSlmQuads*256*4
-// pixels apart within the workgroup's span; each group is 12 image bytes
-// (3 dwords) and 12 floats each of mean and variance (3 x 16 B), naturally
-// aligned. All loads are issued before any arithmetic.
+// A workgroup converts 4 x kWavePixels consecutive pixels of one view
+// (grid.y = view); wave w takes the w-th quarter.
 __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
 {
-    const SlmView sv = a.view[blockIdx.y];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * 4 * kSlmQuads) + threadIdx.x * 4;
-    Quad q[kSlmQuads];
-    bool full[kSlmQuads];
-#pragma unroll
-    for (int t = 0; t < kSlmQuads; ++t) {
-        const int64_t p0 = base + t * 1024;
-        full[t] = p0 + 4 <= sv.npix;
-        if (full[t]) load_quad(sv, p0, q[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < kSlmQuads; ++t) {
-        const int64_t p0 = base + t * 1024;
-        if (full[t])
-            *reinterpret_cast<f32x4 *>(a.lmap + sv.map_off + p0) = quad_log2slm(q[t], a.k0);
-        else if (p0 < sv.npix)
-            tail_pixels(sv, a.lmap, a.k0, p0);
-    }
+    __shared__ SlmStage stage[4];
+    const SlmView &sv = a.view[blockIdx.y];
+    const int wave = static_cast<int>(threadIdx.x >> 6);
+    const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * kWavePixels;
+    float *out = a.lmap + sv.map_off;
+    if (p0 + kWavePixels <= sv.npix)
+        slm_wave(sv.img, sv.mean, sv.var, out, p0, a.k0, stage[wave]);
+    else if (p0 < sv.npix)
+        slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, a.k0);
 }
 
 // Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,
 // 64-lane waves are TX x (64/TX) slabs, one voxel thick in z) and KZ
 // consecutive z-slices; each lane owns one column segment of KZ voxels.
+// Logical tile b enumerates (x tile, y tile, z slab) with x fastest.
 template <int TX, int TY, int KZ, int SAMPLING>
-__global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
+__device__ __forceinline__ void fuse_tile(const FuseArgs &a, int64_t b)
 {
     const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
     const int64_t ntile = static_cast<int64_t>(ntx) * nty;
-    const int64_t nb = ntile * ((a.nz + KZ - 1) / KZ);
-    const int64_t b = xcd_remap(blockIdx.x, nb);
     const int64_t zc = b / ntile;
     const int t = static_cast<int>(b - zc * ntile);
     const int tyi = t / ntx, txi = t - tyi * ntx;
@@ -104,6 +49,71 @@ __global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
     const GridDesc gd{a.nx, a.ny, a.nz, a.ox, a.oy, a.oz, a.h};
     fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return a.view[v]; }, a.n, a.lmap, gd, i, j, k0,
                               a.L0, a.tau, a.post, a.occ);
+}
+
+template <int TX, int TY, int KZ>
+__host__ __device__ int64_t tile_count_of(const FuseArgs &a)
+{
+    return static_cast<int64_t>((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) * ((a.nz + KZ - 1) / KZ);
+}
+
+template <int TX, int TY, int KZ, int SAMPLING>
+__global__ __launch_bounds__(TX * TY) void fuse_kernel(FuseArgs a)
+{
+    fuse_tile<TX, TY, KZ, SAMPLING>(a, xcd_remap(blockIdx.x, tile_count_of<TX, TY, KZ>(a)));
+}
+
+// Round r of the pipelined launch is a likelihood round (sr >= 0) or a fusion
+// round (fr >= 0): one likelihood round to kPipeFuse fusion rounds while both
+// last, then the rest of whichever is left.
+constexpr int kPipeFuse = 2;
+
+__device__ __forceinline__ void pipe_role(int r, int slm_rounds, int fuse_rounds, int &sr, int &fr)
+{
+    const int full = min(slm_rounds, fuse_rounds / kPipeFuse);
+    sr = fr = -1;
+    if (r < full * (1 + kPipeFuse)) {
+        const int cyc = r / (1 + kPipeFuse), pos = r - cyc * (1 + kPipeFuse);
+        if (pos == 0) sr = cyc; else fr = cyc * kPipeFuse + pos - 1;
+        return;
+    }
+    const int rest = r - full * (1 + kPipeFuse), sl = slm_rounds - full;
+    if (rest < sl) sr = full + rest; else fr = full * kPipeFuse + rest - sl;
+}
+
+// Likelihood maps of the next frame (Eq. 1-2, SlmArgs) and fusion of the
+// current frame (Eq. 3-9, FuseArgs, maps written by an earlier launch) in one
+// launch; the two parts share no data. Workgroups come in rounds of kNumXcd
+// consecutive ones, which the dispatcher places one per XCD; a round is either
+// kNumXcd likelihood workgroups (4 x kWavePixels pixels each) or kNumXcd
+// fusion tiles. The likelihood part is HBM-bound and the fusion part bound by
+// its gathers and arithmetic, so interleaving them keeps both busy. The fusion
+// tiles of one XCD form one contiguous range, as in fuse_kernel.
+template <int TX, int TY, int KZ, int SAMPLING>
+__global__ __launch_bounds__(TX * TY) void pipe_kernel(SlmArgs s, FuseArgs f, PipeArgs p)
+{
+    static_assert(TX * TY == 256, "four waves per workgroup");
+    __shared__ SlmStage stage[4];
+    const int round = static_cast<int>(blockIdx.x) / kNumXcd, x = static_cast<int>(blockIdx.x) % kNumXcd;
+    int sr, fr;
+    pipe_role(round, p.slm_rounds, p.fuse_rounds, sr, fr);
+    if (sr >= 0) {
+        const int sb = sr * kNumXcd + x;
+        if (sb >= s.n * p.slm_per_view) return;
+        const int v = sb / p.slm_per_view;
+        const SlmView &sv = s.view[v];
+        const int wave = static_cast<int>(threadIdx.x >> 6);
+        const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * 4 + wave) * kWavePixels;
+        float *out = s.lmap + sv.map_off;
+        if (p0 + kWavePixels <= sv.npix)
+            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave]);
+        else if (p0 < sv.npix)
+            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0);
+    } else {
+        const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + fr;
+        if (tile >= p.fuse_tiles) return;
+        fuse_tile<TX, TY, KZ, SAMPLING>(f, tile);
+    }
 }
 
 __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)
@@ -116,6 +126,35 @@ __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64
 constexpr TileCfg kTiles[] = {
     {8, 32, 4}, {8, 32, 8}, {8, 16, 4}, {8, 32, 2}, {32, 8, 4}, {16, 16, 4},
 };
+
+template <int TX, int TY, int KZ, int S>
+hipError_t launch_pipe_t(const SlmArgs &sa, const FuseArgs &fa, int64_t max_npix, hipStream_t s)
+{
+    PipeArgs p{};
+    const int64_t per_view = sa.n > 0 ? (max_npix + 4 * kWavePixels - 1) / (4 * kWavePixels) : 0;
+    const int64_t slm_blocks = per_view * sa.n;
+    const int64_t tiles = fa.post ? tile_count_of<TX, TY, KZ>(fa) : 0;
+    p.slm_per_view = static_cast<int32_t>(per_view);
+    p.slm_rounds = static_cast<int32_t>((slm_blocks + kNumXcd - 1) / kNumXcd);
+    p.fuse_rounds = static_cast<int32_t>((tiles + kNumXcd - 1) / kNumXcd);
+    p.fuse_tiles = tiles;
+    const int64_t blocks = static_cast<int64_t>(p.slm_rounds + p.fuse_rounds) * kNumXcd;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((pipe_kernel<TX, TY, KZ, S>), dim3(static_cast<unsigned>(blocks)), dim3(TX * TY), 0, s, sa, fa, p);
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_pipe_s(const SlmArgs &sa, const FuseArgs &fa, int tile, int64_t max_npix, hipStream_t s)
+{
+    switch (tile) {
+    case 1: return launch_pipe_t<8, 32, 8, S>(sa, fa, max_npix, s);
+    case 3: return launch_pipe_t<8, 32, 2, S>(sa, fa, max_npix, s);
+    case 4: return launch_pipe_t<32, 8, 4, S>(sa, fa, max_npix, s);
+    case 5: return launch_pipe_t<16, 16, 4, S>(sa, fa, max_npix, s);
+    default: return launch_pipe_t<8, 32, 4, S>(sa, fa, max_npix, s);    // tile 0; tile 2 has 128 lanes
+    }
+}
 
 template <int S>
 hipError_t launch_fuse_s(const FuseArgs &a, int tile, hipStream_t s)
@@ -144,7 +183,7 @@ int default_tile() { return 0; }
 
 hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s)
 {
-    const int64_t per_block = 256 * 4 * kSlmQuads;
+    const int64_t per_block = 4 * kWavePixels;
     const dim3 grid(static_cast<unsigned>((max_npix + per_block - 1) / per_block), static_cast<unsigned>(a.n));
     hipLaunchKernelGGL(slm_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -154,6 +193,13 @@ hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s)
 {
     return sampling == PSFS_BILINEAR ? launch_fuse_s<PSFS_BILINEAR>(a, tile, s)
                                      : launch_fuse_s<PSFS_NEAREST>(a, tile, s);
+}
+
+hipError_t launch_pipeline(const SlmArgs &sa, const FuseArgs &fa, int tile, int sampling, int64_t max_npix,
+                           hipStream_t s)
+{
+    return sampling == PSFS_BILINEAR ? launch_pipe_s<PSFS_BILINEAR>(sa, fa, tile, max_npix, s)
+                                     : launch_pipe_s<PSFS_NEAREST>(sa, fa, tile, max_npix, s);
 }
 
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s)

@@ -55,6 +55,15 @@ struct FuseArgs {
     float tau;                          // threshold on the posterior
 };
 
+// Shape of the pipelined launch (likelihood of the next frame + fusion of
+// the current one).
+struct PipeArgs {
+    int32_t slm_per_view;               // likelihood workgroups per view
+    int32_t slm_rounds;                 // ceil(views * slm_per_view / kNumXcd)
+    int32_t fuse_rounds;                // ceil(fuse_tiles / kNumXcd)
+    int64_t fuse_tiles;
+};
+
 // Differentiable variant: bilinear logits, BCE loss and adjoint (one view
 // geometry per view with the raw camera matrix).
 struct DiffArgs {
@@ -131,6 +140,9 @@ int default_tile();
 
 hipError_t launch_slm(const SlmArgs &a, int64_t max_npix, hipStream_t s);
 hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s);
+// sa.n == 0: no likelihood part; fa.post == nullptr: no fusion part.
+hipError_t launch_pipeline(const SlmArgs &sa, const FuseArgs &fa, int tile, int sampling, int64_t max_npix,
+                           hipStream_t s);
 int64_t diff_fwd_blocks(int nx, int ny, int nz);
 int64_t diff_bwd_blocks(int nx, int ny, int nz);
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);

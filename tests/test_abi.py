@@ -144,6 +144,31 @@ def test_not_ready_and_pointer_checks(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_pipeline_step_validation_without_device(lib):
+    h = _plan(lib)
+    fake, fake2 = C.c_void_p(0x100000), C.c_void_p(0x200000)
+    imgs = L.ptr_array([0x100000, 0x100000])
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_pipeline_step(h, imgs, fake, fake2, fake, None, None) == -3   # grid missing
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert lib.psfs_pipeline_step(h, None, None, None, None, None, None) == 0    # nothing to do
+    assert lib.psfs_pipeline_step(h, imgs, fake, None, None, None, None) == -3   # backgrounds missing
+    assert lib.psfs_set_background(h, 0, fake, fake) == 0
+    assert lib.psfs_set_background(h, 1, fake, fake) == 0
+    assert lib.psfs_pipeline_step(h, imgs, None, None, None, None, None) == -1   # no lmap_next
+    assert lib.psfs_pipeline_step(h, imgs, C.c_void_p(0x100004), None, None, None, None) == -1
+    assert lib.psfs_pipeline_step(h, L.ptr_array([0x100000, 0x100002]), fake, None, None, None, None) == -1
+    assert lib.psfs_pipeline_step(h, None, None, None, None, fake, None) == -1   # occupancy without posterior
+    assert lib.psfs_pipeline_step(h, None, None, None, fake, None, None) == -1   # no lmap_cur
+    assert lib.psfs_pipeline_step(h, None, None, fake, C.c_void_p(0x100008), None, None) == -1
+    # 128 floats of maps: [0x100000, 0x100200) overlaps a buffer starting 0x100100
+    assert lib.psfs_pipeline_step(h, imgs, fake, C.c_void_p(0x100100), fake2, None, None) == -1
+    assert "overlap" in lib.psfs_last_error().decode()
+    lib.psfs_plan_destroy(h)
+
+
 def test_empty_work_is_a_no_op_without_device(lib):
     h = _plan(lib)
     assert lib.psfs_set_cameras(h, 0, None) == 0
