@@ -27,6 +27,38 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E spec
 
+# HBM traffic of one pipe_kernel launch on this workload from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
+# dispatches of `bench.py --steps 24 --warmup 6 --no-cpu --no-batch --no-diff
+# --calibrate-copy`), each scaled by what the counter reads for the calibration
+# kernel (torch.neg over 256 MiB: FETCH_SIZE 131080 KiB for 262144 KiB read,
+# x2.0; WRITE_SIZE 262144 KiB for 262144 KiB written, x1.0). The figures hold
+# for the kernel sources they were taken on (SHA-256 of the files below); once
+# those change, traffic is reported as null until the counters are taken again.
+PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
+                        "paper_1311_6811_amd/csrc/psfs_internal.h")
+PIPE_COUNTERS = {"sources_sha256": "2af0b9272a5d95b42d1b1ad215cf8343dacd0e61f2f1b3c50a4d4655294b48b4",
+                 "fetch_kib": 38281.3, "fetch_scale": 2.0, "write_kib": 20049.1, "write_scale": 1.0,
+                 "l2_hit_rate": 0.655}
+
+
+def sources_sha256() -> str:
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for rel in PIPE_COUNTER_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pipe_traffic():
+    """Measured HBM bytes per pipe_kernel launch, or None if the kernel changed."""
+    c = PIPE_COUNTERS
+    if sources_sha256() != c["sources_sha256"]:
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -180,12 +212,11 @@ def main():
     print(f"[bench] {done} pipelined steps, {ms * 1e3:.2f} us/step", file=sys.stderr, flush=True)
     ms_single, _ = timed(single, steps, args.warmup, graph)
     print(f"[bench] single-frame path (two launches) {ms_single * 1e3:.2f} us/frame", file=sys.stderr, flush=True)
-    # per-launch durations: HIP events on the launch stream around each launch
-    ev_n = min(steps, 240)
-    us_pipe = launch_us(torch, stream, step, ev_n)
-    us_l = launch_us(torch, stream, only_lmap, ev_n)
-    us_f = launch_us(torch, stream, only_fuse, ev_n)
-    print(f"[bench] per launch: pipe {us_pipe:.2f} us, likelihood {us_l:.2f} us, fusion {us_f:.2f} us",
+    # the two kernels of the single-frame path alone (HIP events on the launch
+    # stream around graph replays of back-to-back launches)
+    ms_l, _ = timed(only_lmap, steps, args.warmup, graph)
+    ms_f, _ = timed(only_fuse, steps, args.warmup, graph)
+    print(f"[bench] likelihood alone {ms_l * 1e3:.2f} us, fusion alone {ms_f * 1e3:.2f} us",
           file=sys.stderr, flush=True)
 
     # parity spot check of the timed configuration on sampled voxels
@@ -201,12 +232,15 @@ def main():
     un = ref.ncombo == 1
     max_err = float(np.abs(got - ref.post)[un].max())
 
-    # roofline of the step's one kernel: algorithmic HBM bytes per launch are
-    # the frame's inputs (image + mean + variance, 27 B/pixel) and outputs
-    # (posterior + occupancy, 5 B/voxel); the maps are an intermediate
+    # roofline of the step's one kernel (pipe_kernel, one launch per step, so
+    # its average launch duration is the HIP-event time per step above):
+    # algorithmic HBM bytes per launch are the frame's inputs (image + mean +
+    # variance, 27 B/pixel) and outputs (posterior + occupancy, 5 B/voxel); the
+    # likelihood maps are an intermediate
     step_bytes = 27 * npix + 5 * V
-    dom, dom_us, dom_bytes = "pipe_kernel", us_pipe, step_bytes
-    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    dom, dom_bytes = "pipe_kernel", step_bytes
+    achieved = dom_bytes / (ms * 1e-3) / 1e9
+    traffic = pipe_traffic() if graph else None
 
     diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
@@ -247,10 +281,11 @@ def main():
                    "voxels": V, "views": n, "pixels": npix},
         "frames_per_s": 1e3 / ms,
         "single_frame_path_us": ms_single * 1e3,
-        "kernels_us": {"pipe_kernel": us_pipe, "slm_kernel": us_l, "fuse_kernel": us_f},
+        "kernels_us": {"pipe_kernel": ms * 1e3, "slm_kernel": ms_l * 1e3, "fuse_kernel": ms_f * 1e3},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": dom_bytes},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom_bytes,
+                     "l2_hit_rate": PIPE_COUNTERS["l2_hit_rate"] if traffic is not None else None},
         "step_roofline": {"algorithmic_bytes": step_bytes,
                           "achieved_GBs": step_bytes / (ms * 1e-3) / 1e9,
                           "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -260,22 +295,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def launch_us(torch, stream, fn, count):
-    """Mean duration of one launch of fn (microseconds): a pair of HIP events
-    recorded on the launch stream around every launch, eager launches."""
-    with torch.cuda.stream(stream):
-        for i in range(6):
-            fn(i)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
-        for i, (a, b) in enumerate(ev):
-            a.record(stream)
-            fn(i)
-            b.record(stream)
-        torch.cuda.synchronize()
-    return 1e3 * sum(a.elapsed_time(b) for a, b in ev) / count
 
 
 def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
