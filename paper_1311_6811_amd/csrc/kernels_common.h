@@ -299,64 +299,62 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
         const int i_lo = i - (lane % TX), j_lo = j - (lane / TX);
         const uint32_t inside = wave_inside_mask(views, n, a, i_lo, i_lo + TX - 1, j_lo, j_lo + 64 / TX - 1, k0,
                                                  k0 + KZ - 1);
-        // Views are taken kVB at a time: all kVB*KZ byte offsets first, then
-        // all gathers, then the adds in view order, so a wave keeps up to
-        // kVB*KZ loads in flight. Gathers are raw buffer loads from the view's
-        // map (32-bit offsets, W*H < 2^30): a voxel-view outside its image
-        // gets an offset past the end, for which the hardware returns 0, i.e.
-        // adds nothing; a slot past the last view loads the same way.
-        constexpr int kVB = 4;
-        for (int v0 = 0; v0 < n; v0 += kVB) {
-            uint32_t off[kVB][KZ];
-            __amdgpu_buffer_rsrc_t rsrc[kVB];
+        // Software pipeline over the views: the byte offsets of view v are
+        // computed and its KZ gathers issued before the values of view v-1
+        // are added, so every wave keeps one view's gathers in flight while
+        // it does the next view's arithmetic (adds stay in view order).
+        // Gathers are raw buffer loads from the view's map (32-bit offsets,
+        // W*H < 2^30): a voxel-view outside its image gets an offset past the
+        // end, for which the hardware returns 0, i.e. adds nothing.
+        auto offsets = [&](int v, uint32_t (&off)[KZ], __amdgpu_buffer_rsrc_t &rsrc) {
+            const ViewGeom &g = views(v);
+            const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+            rsrc = map_rsrc(lmap + g.map_off, W * H * 4u);
+            const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+            const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+            const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+            if (inside & (1u << v)) {
+                // every lane lands inside the image: truncation is the floor
 #pragma unroll
-            for (int q = 0; q < kVB; ++q) {
-                const int v = v0 + q;
-                if (v >= n) {
-                    rsrc[q] = rsrc[0];
-#pragma unroll
-                    for (int kk = 0; kk < KZ; ++kk) off[q][kk] = 0xFFFFFFFFu;
-                    continue;
+                for (int kk = 0; kk < KZ; ++kk) {
+                    const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
+                    const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
+                    const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
+                    off[kk] = (__umul24(y, W) + x) * 4u;
                 }
-                const ViewGeom &g = views(v);
-                const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
-                rsrc[q] = map_rsrc(lmap + g.map_off, W * H * 4u);
-                const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
-                const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
-                const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
-                if (inside & (1u << v)) {
-                    // every lane lands inside the image: truncation is the floor
+            } else {
 #pragma unroll
-                    for (int kk = 0; kk < KZ; ++kk) {
-                        const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
-                        const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
-                        const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
-                        off[q][kk] = (__umul24(y, W) + x) * 4u;
-                    }
-                } else {
-#pragma unroll
-                    for (int kk = 0; kk < KZ; ++kk) {
-                        const float c = fmaf(g.P[10], Z[kk], cx);
-                        const float r = __builtin_amdgcn_rcpf(c);
-                        const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
-                        const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
-                        const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
-                        off[q][kk] = ok ? (__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)) * 4u
-                                        : 0xFFFFFFFFu;
-                    }
+                for (int kk = 0; kk < KZ; ++kk) {
+                    const float c = fmaf(g.P[10], Z[kk], cx);
+                    const float r = __builtin_amdgcn_rcpf(c);
+                    const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                    const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                    const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
+                    off[kk] = ok ? (__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)) * 4u
+                                 : 0xFFFFFFFFu;
                 }
             }
-            float val[kVB][KZ];
+        };
+        if (n > 0) {
+            uint32_t off[KZ];
+            __amdgpu_buffer_rsrc_t rsrc;
+            float val[KZ];
+            offsets(0, off, rsrc);
 #pragma unroll
-            for (int q = 0; q < kVB; ++q) {
+            for (int kk = 0; kk < KZ; ++kk) val[kk] = map_load(rsrc, off[kk]);
+            for (int v = 1; v < n; ++v) {
+                offsets(v, off, rsrc);
+                float next[KZ];
 #pragma unroll
-                for (int kk = 0; kk < KZ; ++kk) val[q][kk] = map_load(rsrc[q], off[q][kk]);
+                for (int kk = 0; kk < KZ; ++kk) next[kk] = map_load(rsrc, off[kk]);
+#pragma unroll
+                for (int kk = 0; kk < KZ; ++kk) {
+                    L[kk] += val[kk];
+                    val[kk] = next[kk];
+                }
             }
 #pragma unroll
-            for (int q = 0; q < kVB; ++q) {
-#pragma unroll
-                for (int kk = 0; kk < KZ; ++kk) L[kk] += val[q][kk];
-            }
+            for (int kk = 0; kk < KZ; ++kk) L[kk] += val[kk];
         }
     } else {
         // Bilinear weights turn a projection error du into an error
