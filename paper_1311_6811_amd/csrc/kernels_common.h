@@ -335,26 +335,39 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
                 }
             }
         };
-        if (n > 0) {
-            uint32_t off[KZ];
-            __amdgpu_buffer_rsrc_t rsrc;
-            float val[KZ];
-            offsets(0, off, rsrc);
+        // Two value sets used in turn (no register copies, which would make
+        // the wave wait for the gathers it just issued).
+        uint32_t off[KZ];
+        __amdgpu_buffer_rsrc_t rsrc;
+        float va[KZ], vb[KZ];
+        auto gather = [&](float (&val)[KZ]) {
 #pragma unroll
             for (int kk = 0; kk < KZ; ++kk) val[kk] = map_load(rsrc, off[kk]);
-            for (int v = 1; v < n; ++v) {
-                offsets(v, off, rsrc);
-                float next[KZ];
-#pragma unroll
-                for (int kk = 0; kk < KZ; ++kk) next[kk] = map_load(rsrc, off[kk]);
-#pragma unroll
-                for (int kk = 0; kk < KZ; ++kk) {
-                    L[kk] += val[kk];
-                    val[kk] = next[kk];
-                }
-            }
+        };
+        auto accumulate = [&](const float (&val)[KZ]) {
 #pragma unroll
             for (int kk = 0; kk < KZ; ++kk) L[kk] += val[kk];
+        };
+        if (n > 0) {
+            offsets(0, off, rsrc);
+            gather(va);
+            int v = 1;
+            for (; v + 1 < n; v += 2) {
+                offsets(v, off, rsrc);
+                gather(vb);
+                accumulate(va);
+                offsets(v + 1, off, rsrc);
+                gather(va);
+                accumulate(vb);
+            }
+            if (v < n) {
+                offsets(v, off, rsrc);
+                gather(vb);
+                accumulate(va);
+                accumulate(vb);
+            } else {
+                accumulate(va);
+            }
         }
     } else {
         // Bilinear weights turn a projection error du into an error
