@@ -242,6 +242,7 @@ def main():
     achieved = dom_bytes / (ms * 1e-3) / 1e9
     traffic = pipe_traffic() if graph else None
 
+    surface = measure_surface(torch, psfs, slots[0], timed_graph, args)
     diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
 
@@ -290,11 +291,35 @@ def main():
                           "achieved_GBs": step_bytes / (ms * 1e-3) / 1e9,
                           "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "parity_max_abs_err": max_err,
+        "surface": surface,
         "fwd_bwd": diff,
         "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_surface(torch, psfs, slot, timed_graph, args):
+    """Smoothing + threshold + surface list of the headline posterior (three
+    launches), replayed from a HIP graph."""
+    plan, post = slot["plan"], slot["post"]
+    g = plan.grid
+    V = g.nx * g.ny * g.nz
+    occ = torch.empty_like(post, dtype=torch.uint8)
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    count = torch.empty((), dtype=torch.int64, device="cuda")
+    ws = torch.empty(max(plan.surface_workspace_bytes(), 4), dtype=torch.uint8, device="cuda")
+
+    def f():
+        plan.surface(post, occ=occ, out=out, count=count, workspace=ws)
+
+    ms = timed_graph([f], max(20, args.steps // 10), 5)
+    n = int(count.item())
+    algo = 4 * V + 1 * V + 4 * n
+    print(f"[bench] surface extraction {ms * 1e3:.2f} us ({n} surface voxels)", file=sys.stderr, flush=True)
+    return {"workload": "3x3x3 smoothing + threshold + surface list of the 128^3 posterior",
+            "us": ms * 1e3, "surface_voxels": n, "algorithmic_bytes": algo,
+            "achieved_GBs": algo / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):

@@ -173,6 +173,35 @@ int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float 
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,
                    void *stream);
 
+/* ------------------------------------------- smoothing and surface voxels */
+
+/* Workspace of psfs_surface (per-block counts). 0 if the grid is unset. */
+size_t psfs_surface_workspace_bytes(const psfs_plan *plan);
+
+/* The step after the posterior (Sec. 2.2.2, last paragraph; the paper merges
+ * smoothing with voxel generation, Sec. 3.3.1, and removes inner voxels on the
+ * CPU, Sec. 3.3.3 step e). For the plan's grid and threshold:
+ *   smoothed[v] = mean of posterior over the 3x3x3 voxels around v that lie
+ *                 in the grid (FP32, summed in a fixed order);
+ *   occ[v]      = smoothed[v] > threshold (u8 0/1);
+ *   surface     = ascending linear indices (k*ny + j)*nx + i of the occupied
+ *                 voxels with at least one of their 6 face neighbours
+ *                 unoccupied or outside the grid.
+ * Arguments:
+ *   posterior_dev  FP32 [nz][ny][nx] (4-byte aligned)
+ *   smoothed_dev   nullable FP32 [nz][ny][nx]
+ *   occ_dev        u8 [nz][ny][nx], required (the surface test reads it back)
+ *   surface_dev    int32 [capacity]; the first min(count, capacity) entries
+ *                  are written (NULL allowed when capacity == 0)
+ *   count_dev      one int64 on the device: the number of surface voxels,
+ *                  also when it exceeds capacity
+ *   workspace      psfs_surface_workspace_bytes bytes, 4-byte aligned
+ * Needs only the grid (PSFS_E_NOT_READY otherwise); cameras are not used.
+ * An empty grid writes count 0. */
+int psfs_surface(psfs_plan *plan, const float *posterior_dev, float *smoothed_dev, uint8_t *occ_dev,
+                 int32_t *surface_dev, int64_t capacity, int64_t *count_dev, void *workspace_dev,
+                 size_t workspace_bytes, void *stream);
+
 /* ---------------------------------------- differentiable variant (bilinear) */
 
 /* Workspace of psfs_diff_forward / psfs_diff_backward: likelihood maps,

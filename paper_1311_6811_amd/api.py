@@ -205,6 +205,34 @@ class Plan:
             cur = _dev(lmap_cur, torch.float32, "lmap_cur")
         L.check(L.lib().psfs_pipeline_step(self._h, ims, nxt, cur, pp, op, _stream()))
 
+    # ------------------------------------- smoothing and surface voxels
+    def surface_workspace_bytes(self) -> int:
+        return int(L.lib().psfs_surface_workspace_bytes(self._h))
+
+    def surface(self, posterior: torch.Tensor, capacity: Optional[int] = None, occ=None, smoothed=None,
+                want_smoothed: bool = False, out=None, count=None, workspace=None) -> "Surface":
+        """Smoothing (3x3x3 in-grid mean), threshold and surface voxels of a
+        posterior grid. Asynchronous: ``Surface.indices()`` synchronises."""
+        g = self.grid
+        shape = (g.nz, g.ny, g.nx)
+        nvox = g.nx * g.ny * g.nz
+        cap = nvox if capacity is None else int(capacity)
+        occ = occ if occ is not None else torch.empty(shape, dtype=torch.uint8, device="cuda")
+        if want_smoothed and smoothed is None:
+            smoothed = torch.empty(shape, dtype=torch.float32, device="cuda")
+        out = out if out is not None else torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        count = count if count is not None else torch.empty((), dtype=torch.int64, device="cuda")
+        ws = workspace if workspace is not None else torch.empty(max(self.surface_workspace_bytes(), 4),
+                                                                 dtype=torch.uint8, device="cuda")
+        if out.numel() < cap:
+            raise ValueError("out holds fewer than capacity entries")
+        L.check(L.lib().psfs_surface(self._h, _dev(posterior, torch.float32, "posterior", shape),
+                                     _dev(smoothed, torch.float32, "smoothed", shape) if smoothed is not None else None,
+                                     _dev(occ, torch.uint8, "occ", shape), _dev(out, torch.int32, "out"), cap,
+                                     _dev(count, torch.int64, "count"), _dev(ws, torch.uint8, "workspace"),
+                                     ws.numel(), _stream()))
+        return Surface(occ, smoothed, out, count, cap)
+
     # ------------------------------------------- differentiable variant
     def diff_workspace_bytes(self) -> int:
         return int(L.lib().psfs_diff_workspace_bytes(self._h))
@@ -255,6 +283,19 @@ class Plan:
                                            workspace.numel(), _stream()))
         self._keep["grad_loss"] = gl
         return gmeans, gvars, gP[: self.n]
+
+
+class Surface:
+    """Result of Plan.surface: occupancy, optional smoothed posterior, and
+    the surface-voxel list (capacity-sized buffer + device count)."""
+
+    def __init__(self, occ, smoothed, out, count, capacity):
+        self.occ, self.smoothed, self.out, self.count, self.capacity = occ, smoothed, out, count, capacity
+
+    def indices(self) -> torch.Tensor:
+        """Ascending int32 linear indices (synchronises on the count)."""
+        n = int(self.count.item())
+        return self.out[:min(n, self.capacity)]
 
 
 class Pipeline:

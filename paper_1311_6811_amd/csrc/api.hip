@@ -509,6 +509,57 @@ int psfs_threshold(const float *posterior_dev, int64_t nvox_, float tau, uint8_t
     PSFS_GUARD_END
 }
 
+size_t psfs_surface_workspace_bytes(const psfs_plan *plan)
+{
+    if (!plan || !plan->has_grid) return 0;
+    const int64_t V = nvox(plan->grid);
+    return align256(static_cast<size_t>(surface_blocks(V)) * sizeof(int32_t)) + align256(static_cast<size_t>(V));
+}
+
+int psfs_surface(psfs_plan *plan, const float *posterior_dev, float *smoothed_dev, uint8_t *occ_dev,
+                 int32_t *surface_dev, int64_t capacity, int64_t *count_dev, void *workspace_dev,
+                 size_t workspace_bytes, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (!plan->has_grid) return fail(PSFS_E_NOT_READY, "grid not set");
+    if (capacity < 0) return fail(PSFS_E_RANGE, "capacity must be >= 0");
+    if (!count_dev || !aligned(count_dev, 8)) return fail(PSFS_E_ARG, "count must be an 8-byte aligned device pointer");
+    const int64_t V = nvox(plan->grid);
+    if (V > 0) {
+        if (!posterior_dev || !aligned(posterior_dev, 4)) return fail(PSFS_E_ARG, "posterior must be a 4-byte aligned device pointer");
+        if (smoothed_dev && !aligned(smoothed_dev, 4)) return fail(PSFS_E_ARG, "smoothed must be 4-byte aligned");
+        if (!occ_dev) return fail(PSFS_E_ARG, "occupancy output is NULL");
+        if (capacity > 0 && (!surface_dev || !aligned(surface_dev, 4)))
+            return fail(PSFS_E_ARG, "surface must be a 4-byte aligned device pointer");
+        const size_t need = psfs_surface_workspace_bytes(plan);
+        if (!workspace_dev || workspace_bytes < need || !aligned(workspace_dev, 256))
+            return fail(PSFS_E_WORKSPACE, "surface workspace needs %zu bytes, 256-byte aligned (got %zu)", need,
+                        workspace_bytes);
+    }
+    int rc = check_device();
+    if (rc) return rc;
+    SurfArgs a{};
+    a.post = posterior_dev;
+    a.smoothed = smoothed_dev;
+    a.occ = occ_dev;
+    a.out = surface_dev;
+    a.capacity = capacity;
+    a.count = count_dev;
+    a.counts = static_cast<int32_t *>(workspace_dev);
+    a.nvox = V;
+    a.nblocks = static_cast<int32_t>(surface_blocks(V));
+    a.nx = plan->grid.nx;
+    a.ny = plan->grid.ny;
+    a.nz = plan->grid.nz;
+    a.flags = static_cast<uint8_t *>(workspace_dev) + align256(static_cast<size_t>(a.nblocks) * sizeof(int32_t));
+    a.tau = plan->params.threshold;
+    hipError_t e = launch_surface(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "surface kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
 size_t psfs_diff_workspace_bytes(const psfs_plan *plan)
 {
     if (!plan || plan->n < 0 || !plan->has_grid) return 0;

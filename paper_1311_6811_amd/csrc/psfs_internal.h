@@ -130,6 +130,22 @@ struct BatchArgs {
     float k0, L0, tau;
 };
 
+// Smoothing, threshold and surface extraction of one posterior grid.
+struct SurfArgs {
+    const float *post;                  // [nz][ny][nx]
+    float *smoothed;                    // nullable, [nz][ny][nx]
+    uint8_t *occ;                       // [nz][ny][nx]
+    int32_t *out;                       // ascending surface indices, first `capacity`
+    int64_t capacity;
+    int64_t *count;                     // device: number of surface voxels
+    int32_t *counts;                    // workspace: per-block surface counts
+    uint8_t *flags;                     // workspace: surface flag per voxel
+    int64_t nvox;
+    int32_t nblocks;
+    int32_t nx, ny, nz;
+    float tau;
+};
+
 struct TileCfg {
     int tx, ty, kz;                     // x-by-y lanes per workgroup, z voxels per lane
 };
@@ -153,5 +169,7 @@ int64_t batch_bricks(int nx, int ny, int nz, int tile);
 int batch_fuse_occupancy(int tile, int sampling);
 hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid, int fuse_grid, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
+int64_t surface_blocks(int64_t nvox);
+hipError_t launch_surface(const SurfArgs &a, hipStream_t s);   // a.nvox == 0: writes count 0 only
 
 }  // namespace psfs

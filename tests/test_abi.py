@@ -169,6 +169,26 @@ def test_pipeline_step_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_surface_validation_without_device(lib):
+    h = _plan(lib)
+    fake = C.c_void_p(0x100000)
+    assert lib.psfs_surface_workspace_bytes(h) == 0
+    assert lib.psfs_surface(h, fake, None, fake, fake, 10, fake, fake, 4096, None) == -3   # grid missing
+    g = psfs.make_grid(40, 30, 20, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    need = lib.psfs_surface_workspace_bytes(h)
+    assert need == 256 + 24064             # 6 int32 block counts (256 B) + one flag byte per voxel, 256-B rounded
+    assert lib.psfs_surface(h, fake, None, fake, fake, -1, fake, fake, need, None) == -2
+    assert lib.psfs_surface(h, fake, None, fake, fake, 10, None, fake, need, None) == -1
+    assert lib.psfs_surface(h, None, None, fake, fake, 10, fake, fake, need, None) == -1
+    assert lib.psfs_surface(h, fake, None, None, fake, 10, fake, fake, need, None) == -1
+    assert lib.psfs_surface(h, fake, None, fake, None, 10, fake, fake, need, None) == -1
+    assert lib.psfs_surface(h, fake, None, fake, fake, 10, C.c_void_p(0x100004), fake, need, None) == -1
+    assert lib.psfs_surface(h, fake, None, fake, fake, 10, fake, fake, need - 1, None) == -4
+    assert lib.psfs_surface(h, fake, None, fake, fake, 10, fake, None, need, None) == -4
+    lib.psfs_plan_destroy(h)
+
+
 def test_empty_work_is_a_no_op_without_device(lib):
     h = _plan(lib)
     assert lib.psfs_set_cameras(h, 0, None) == 0

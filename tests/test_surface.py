@@ -1,0 +1,112 @@
+"""GPU smoothing, threshold and surface extraction against the FP64 oracle
+(oracle/surface.py). The smoothed posterior is a sum of 27 FP32 values, so it
+matches to ~1e-6; thresholds are chosen away from every smoothed value by
+more than that, so occupancy and the surface list must then match exactly."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+import paper_1311_6811_amd as psfs
+from oracle import surface as SO
+from synth import scene as S
+from tests.gpu_util import plan_for, upload
+
+pytestmark = pytest.mark.gpu
+
+SMOOTH_TOL = 2e-6
+BAND = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def field(shape, seed, sigma=1.5):
+    rng = np.random.default_rng(seed)
+    p = ndimage.gaussian_filter(rng.random(shape), sigma)
+    p = (p - p.min()) / max(p.max() - p.min(), 1e-12)
+    return p.astype(np.float32)
+
+
+def clear_tau(sm, candidates=(0.5, 0.45, 0.55, 0.4, 0.6, 0.35, 0.65)):
+    for t in candidates:
+        if np.min(np.abs(sm - t)) > BAND:
+            return t
+    raise AssertionError("no threshold clear of the smoothed values")
+
+
+def grid_of(shape):
+    nz, ny, nx = shape
+    return S.Grid(nx, ny, nz, np.zeros(3, np.float32), np.float32(0.01))
+
+
+def run(post_np, tau, capacity=None, want_smoothed=True):
+    nz, ny, nx = post_np.shape
+    plan = psfs.Plan(None, grid_of(post_np.shape), threshold=tau)
+    post = torch.from_numpy(np.ascontiguousarray(post_np)).cuda()
+    res = plan.surface(post, capacity=capacity, want_smoothed=want_smoothed)
+    torch.cuda.synchronize()
+    return res
+
+
+def check(post_np, tau=None):
+    sm, _, _ = SO.extract(post_np.astype(np.float64))
+    tau = clear_tau(sm) if tau is None else tau
+    sm, occ, idx = SO.extract(post_np.astype(np.float64), tau)
+    res = run(post_np, tau)
+    got_sm = res.smoothed.cpu().numpy().astype(np.float64)
+    assert np.abs(got_sm - sm).max() <= SMOOTH_TOL
+    assert np.array_equal(res.occ.cpu().numpy(), occ)
+    got = res.indices().cpu().numpy().astype(np.int64)
+    assert int(res.count.item()) == len(idx)
+    assert np.array_equal(got, idx)
+    return len(idx)
+
+
+@pytest.mark.parametrize("shape", [(23, 29, 37), (16, 16, 16), (1, 1, 1), (7, 1, 5), (2, 33, 65), (40, 8, 130)])
+def test_random_fields_ragged_grids(shape):
+    say(f"surface on {shape}")
+    n = check(field(shape, sum(shape)))
+    say(f"  {n} surface voxels")
+
+
+def test_posterior_of_the_headline_workload():
+    say("surface of the 128^3 x 8-view posterior")
+    fr = S.config_frame(1, 0)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    post, _ = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    p = post.cpu().numpy()
+    n = check(p)
+    say(f"  {n} surface voxels of {p.size}")
+    assert n > 1000
+
+
+def test_capacity_smaller_than_count():
+    p = field((20, 24, 28), 5)
+    sm, _, _ = SO.extract(p.astype(np.float64))
+    tau = clear_tau(sm)
+    _, _, idx = SO.extract(p.astype(np.float64), tau)
+    assert len(idx) > 50
+    cap = len(idx) // 3
+    res = run(p, tau, capacity=cap, want_smoothed=False)
+    assert int(res.count.item()) == len(idx)
+    assert np.array_equal(res.out[:cap].cpu().numpy(), idx[:cap])
+    assert res.smoothed is None
+
+
+def test_solid_block_and_empty_grid():
+    p = np.zeros((12, 12, 12), np.float32)
+    p[2:10, 2:10, 2:10] = 1.0
+    sm, occ, idx = SO.extract(p.astype(np.float64), 0.5)
+    res = run(p, 0.5)
+    assert np.array_equal(res.indices().cpu().numpy(), idx)
+    plan = psfs.Plan(None, S.Grid(0, 4, 4, np.zeros(3, np.float32), np.float32(0.1)))
+    res = plan.surface(torch.empty((4, 4, 0), device="cuda"))
+    torch.cuda.synchronize()
+    assert int(res.count.item()) == 0
