@@ -553,6 +553,12 @@ int psfs_surface(psfs_plan *plan, const float *posterior_dev, float *smoothed_de
     a.ny = plan->grid.ny;
     a.nz = plan->grid.nz;
     a.flags = static_cast<uint8_t *>(workspace_dev) + align256(static_cast<size_t>(a.nblocks) * sizeof(int32_t));
+    if (V > 0) {
+        const int64_t nx = a.nx, ny = a.ny;
+        a.step_i = static_cast<int32_t>(256 % nx);
+        a.step_j = static_cast<int32_t>((256 / nx) % ny);
+        a.step_k = static_cast<int32_t>(256 / (nx * ny));
+    }
     a.tau = plan->params.threshold;
     hipError_t e = launch_surface(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "surface kernel launch");

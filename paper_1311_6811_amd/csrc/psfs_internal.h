@@ -143,6 +143,7 @@ struct SurfArgs {
     int64_t nvox;
     int32_t nblocks;
     int32_t nx, ny, nz;
+    int32_t step_i, step_j, step_k;     // 256 voxels as (256 % nx, (256 / nx) % ny, 256 / (nx*ny))
     float tau;
 };
 

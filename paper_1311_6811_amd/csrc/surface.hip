@@ -1,14 +1,13 @@
 // The step after the posterior (Sec. 2.2.2, last paragraph; Sec. 3.3.3 steps
 // d and e): smoothing of the occupancy probabilities, thresholding, and removal
 // of the voxels inside the body, leaving the surface voxels as a compact list.
-//   smooth_surface_kernel  3x3x3 mean over the in-grid neighbours, threshold
-//                          and surface flag in one traversal (the paper
-//                          merges smoothing with voxel generation to save a
-//                          round trip through memory); a surface voxel is
-//                          occupied with an unoccupied or out-of-grid face
-//                          neighbour
-//   surface_count          per block of kSurfBlock consecutive voxels, the
-//                          number of surface flags
+//   smooth_kernel          3x3x3 mean over the in-grid neighbours and the
+//                          threshold in one traversal (the paper merges
+//                          smoothing with voxel generation to save a round
+//                          trip through memory)
+//   surface_flag_kernel    surface flag of every voxel (occupied, with an
+//                          unoccupied or out-of-grid face neighbour) and, per
+//                          block of kSurfBlock consecutive voxels, their count
 //   surface_write          the flagged voxels' linear indices at their place
 //                          in the ascending list (block offset = sum of the
 //                          earlier blocks' counts)
@@ -19,108 +18,105 @@
 namespace psfs {
 namespace {
 
-constexpr int kBX = 32, kBY = 8, kBZ = 4;          // tile of output voxels
+constexpr int kColZ = 8;                            // z-values per lane in smooth_kernel
 constexpr int kSurfBlock = 4096;                    // voxels per compaction block (16 per lane)
+constexpr int kPerLane = kSurfBlock / 256;
 
-// Smoothing, threshold and the surface test in one pass over a tile of
-// kBX x kBY x kBZ output voxels. The surface test needs the occupancy of the
-// face neighbours, hence the smoothed value one voxel beyond the tile, hence
-// the posterior two voxels beyond it. The 3x3x3 sum is separable and taken in
-// one fixed order (x, then y, then z), so a voxel's smoothed value has the
-// same bits whether it is a tile's output or another tile's halo. Cells
-// outside the grid hold posterior 0 and occupancy 0, so "a face neighbour
-// with occupancy 0" covers both an unoccupied and an out-of-grid neighbour.
-constexpr int kPX = kBX + 4, kPY = kBY + 4, kPZ = kBZ + 4;   // posterior, halo 2
-constexpr int kSX = kBX + 2, kSY = kBY + 2, kSZ = kBZ + 2;   // smoothed, halo 1
-
-__global__ __launch_bounds__(256) void smooth_surface_kernel(SurfArgs a)
+// 3x3x3 mean over the in-grid neighbours and threshold. A lane owns kColZ
+// voxels of one (x, y) column: for each plane z it sums the 3 x 3 window of
+// the posterior around (x, y) (rows dy = -1..1, in each row dx = -1..1), then
+// slides a sum of three planes along z; lanes run along x, so each load of the
+// window is one contiguous row of the wave. Out-of-grid cells are skipped and
+// the sum is divided by the number of in-grid cells. One fixed order of the
+// additions for every voxel.
+__global__ __launch_bounds__(256) void smooth_kernel(SurfArgs a)
 {
-    __shared__ float P[kPZ][kPY][kPX];
-    __shared__ float SX[kPZ][kPY][kSX];             // sums over x
-    __shared__ float SXY[kPZ][kSY][kSX];            // sums over x and y
-    __shared__ uint8_t OCC[kSZ][kSY][kSX];
-    const int nbx = (a.nx + kBX - 1) / kBX, nby = (a.ny + kBY - 1) / kBY;
-    const int b = static_cast<int>(blockIdx.x);
-    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int ox = bx * kBX, oy = by * kBY, oz = bz * kBZ;          // first output voxel
-    const int tid = static_cast<int>(threadIdx.x);
-    // all loads of the halo block first, then the LDS stores (one wait)
-    constexpr int kPN = kPX * kPY * kPZ, kPIter = (kPN + 255) / 256;
-    float pv[kPIter];
+    const int nxb = (a.nx + 63) / 64;
+    const int64_t col = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t ncols = static_cast<int64_t>(nxb) * a.ny;
+    const int zb = static_cast<int>(blockIdx.y);
+    if (col >= ncols) return;
+    const int y = static_cast<int>(col / nxb), x = static_cast<int>(col % nxb) * 64 + static_cast<int>(threadIdx.x & 63);
+    if (x >= a.nx) return;
+    const int z0 = zb * kColZ;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    const bool xl = x > 0, xr = x + 1 < a.nx, yl = y > 0, yr = y + 1 < a.ny;
+    auto window = [&](int z) -> float {
+        if (z < 0 || z >= a.nz) return 0.0f;
+        const float *row = a.post + z * plane + static_cast<int64_t>(y) * a.nx + x;
+        float s = 0.0f;
 #pragma unroll
-    for (int r = 0; r < kPIter; ++r) {
-        const int e = tid + 256 * r;
-        const int hx = e % kPX, hy = (e / kPX) % kPY, hz = e / (kPX * kPY);
-        const int gx = ox - 2 + hx, gy = oy - 2 + hy, gz = oz - 2 + hz;
-        const bool in = e < kPN && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz;
-        pv[r] = in ? a.post[(static_cast<int64_t>(gz) * a.ny + gy) * a.nx + gx] : 0.0f;
-    }
-#pragma unroll
-    for (int r = 0; r < kPIter; ++r) {
-        const int e = tid + 256 * r;
-        if (e < kPN) (&P[0][0][0])[e] = pv[r];
-    }
-    __syncthreads();
-    // separable sums, each pass a fixed number of unrolled rounds so that a
-    // thread's LDS reads of all its elements are in flight together
-    constexpr int kN1 = kSX * kPY * kPZ, kN2 = kSX * kSY * kPZ, kN3 = kSX * kSY * kSZ;
-#pragma unroll
-    for (int r = 0; r < (kN1 + 255) / 256; ++r) {
-        const int e = tid + 256 * r;
-        if (e < kN1) {
-            const int sx = e % kSX, hy = (e / kSX) % kPY, hz = e / (kSX * kPY);
-            SX[hz][hy][sx] = (P[hz][hy][sx] + P[hz][hy][sx + 1]) + P[hz][hy][sx + 2];
+        for (int dy = -1; dy <= 1; ++dy) {
+            if ((dy < 0 && !yl) || (dy > 0 && !yr)) continue;
+            const float *r = row + dy * a.nx;
+            float t = r[0];
+            if (xl) t = r[-1] + t;
+            if (xr) t = t + r[1];
+            s += t;
         }
-    }
-    __syncthreads();
+        return s;
+    };
+    float w[kColZ + 2];
 #pragma unroll
-    for (int r = 0; r < (kN2 + 255) / 256; ++r) {
-        const int e = tid + 256 * r;
-        if (e < kN2) {
-            const int sx = e % kSX, sy = (e / kSX) % kSY, hz = e / (kSX * kSY);
-            SXY[hz][sy][sx] = (SX[hz][sy][sx] + SX[hz][sy + 1][sx]) + SX[hz][sy + 2][sx];
-        }
-    }
-    __syncthreads();
-    // smoothed value and occupancy of the tile plus one voxel around it; the
-    // smoothed values go where the posterior was (no longer read)
-    float(*M)[kSY][kSX] = reinterpret_cast<float(*)[kSY][kSX]>(&P[0][0][0]);
-    static_assert(kN3 <= kPX * kPY * kPZ, "smoothed block fits the posterior block");
+    for (int q = 0; q < kColZ + 2; ++q) w[q] = window(z0 - 1 + q);
+    const int cxy = (xl + 1 + xr) * (yl + 1 + yr);
 #pragma unroll
-    for (int r = 0; r < (kN3 + 255) / 256; ++r) {
-        const int e = tid + 256 * r;
-        if (e < kN3) {
-            const int sx = e % kSX, sy = (e / kSX) % kSY, sz = e / (kSX * kSY);
-            const int gx = ox - 1 + sx, gy = oy - 1 + sy, gz = oz - 1 + sz;
-            uint8_t o = 0;
-            if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz) {
-                const int c = ((gx > 0) + 1 + (gx + 1 < a.nx)) * ((gy > 0) + 1 + (gy + 1 < a.ny)) *
-                              ((gz > 0) + 1 + (gz + 1 < a.nz));
-                const float m =
-                    ((SXY[sz][sy][sx] + SXY[sz + 1][sy][sx]) + SXY[sz + 2][sy][sx]) / static_cast<float>(c);
-                o = m > a.tau ? 1 : 0;
-                M[sz][sy][sx] = m;
+    for (int q = 0; q < kColZ; ++q) {
+        const int z = z0 + q;
+        if (z >= a.nz) break;
+        const int c = cxy * ((z > 0) + 1 + (z + 1 < a.nz));
+        const float m = ((w[q] + w[q + 1]) + w[q + 2]) / static_cast<float>(c);
+        const int64_t idx = z * plane + static_cast<int64_t>(y) * a.nx + x;
+        if (a.smoothed) a.smoothed[idx] = m;
+        a.occ[idx] = m > a.tau ? 1 : 0;
+    }
+}
+
+// Surface flags of one compaction block and its count. Lane l of wave w
+// tests voxels base + 256 r + 64 w + l (coalesced neighbour loads); the
+// lane's (i, j, k) is divided out once and then advanced by 256 voxels per
+// step with the carries the host precomputed.
+__global__ __launch_bounds__(256) void surface_flag_kernel(SurfArgs a)
+{
+    __shared__ int part[4];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kSurfBlock;
+    const int64_t v0 = base + threadIdx.x;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    int k = static_cast<int>(v0 / plane);
+    const int64_t rem = v0 - static_cast<int64_t>(k) * plane;
+    int j = static_cast<int>(rem / a.nx);
+    int i = static_cast<int>(rem - static_cast<int64_t>(j) * a.nx);
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kPerLane; ++r) {
+        const int64_t v = v0 + 256 * r;
+        if (v < a.nvox) {
+            bool surf = false;
+            if (a.occ[v]) {
+                surf = i == 0 || i + 1 == a.nx || j == 0 || j + 1 == a.ny || k == 0 || k + 1 == a.nz ||
+                       !a.occ[v - 1] || !a.occ[v + 1] || !a.occ[v - a.nx] || !a.occ[v + a.nx] ||
+                       !a.occ[v - plane] || !a.occ[v + plane];
             }
-            OCC[sz][sy][sx] = o;
+            a.flags[v] = surf ? 1 : 0;
+            c += surf;
         }
+        i += a.step_i;
+        if (i >= a.nx) {
+            i -= a.nx;
+            ++j;
+        }
+        j += a.step_j;
+        if (j >= a.ny) {
+            j -= a.ny;
+            ++k;
+        }
+        k += a.step_k;
     }
-    __syncthreads();
-    const int lx = tid % kBX, ly = tid / kBX;
-    const int gx = ox + lx, gy = oy + ly;
-    if (gx >= a.nx || gy >= a.ny) return;
 #pragma unroll
-    for (int z = 0; z < kBZ; ++z) {
-        const int gz = oz + z;
-        if (gz >= a.nz) break;
-        const int64_t idx = (static_cast<int64_t>(gz) * a.ny + gy) * a.nx + gx;
-        const int sx = lx + 1, sy = ly + 1, sz = z + 1;
-        const uint8_t o = OCC[sz][sy][sx];
-        const bool surf = o && !(OCC[sz][sy][sx - 1] && OCC[sz][sy][sx + 1] && OCC[sz][sy - 1][sx] &&
-                                 OCC[sz][sy + 1][sx] && OCC[sz - 1][sy][sx] && OCC[sz + 1][sy][sx]);
-        if (a.smoothed) a.smoothed[idx] = M[sz][sy][sx];
-        a.occ[idx] = o;
-        a.flags[idx] = surf ? 1 : 0;
-    }
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) a.counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
 // Lane l of a compaction block owns its 16 consecutive voxels
@@ -156,14 +152,6 @@ __device__ __forceinline__ int block_inclusive_scan(int x, int *wave_tot)
     __syncthreads();
     for (int q = 0; q < w; ++q) x += wave_tot[q];
     return x;
-}
-
-__global__ __launch_bounds__(256) void surface_count_kernel(SurfArgs a)
-{
-    __shared__ int wave_tot[4];
-    const int c = __popc(lane_flags(a, static_cast<int64_t>(blockIdx.x) * kSurfBlock));
-    const int incl = block_inclusive_scan(c, wave_tot);
-    if (threadIdx.x == 255) a.counts[blockIdx.x] = incl;
 }
 
 __global__ __launch_bounds__(256) void surface_write_kernel(SurfArgs a)
@@ -222,10 +210,10 @@ hipError_t launch_surface(const SurfArgs &a, hipStream_t s)
         hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, s, a.count);
         return hipGetLastError();
     }
-    const int64_t tiles = static_cast<int64_t>((a.nx + kBX - 1) / kBX) * ((a.ny + kBY - 1) / kBY) *
-                          ((a.nz + kBZ - 1) / kBZ);
-    hipLaunchKernelGGL(smooth_surface_kernel, dim3(static_cast<unsigned>(tiles)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(surface_count_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
+    const int64_t cols = static_cast<int64_t>((a.nx + 63) / 64) * a.ny;
+    const dim3 sg(static_cast<unsigned>((cols + 3) / 4), static_cast<unsigned>((a.nz + kColZ - 1) / kColZ));
+    hipLaunchKernelGGL(smooth_kernel, sg, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(surface_flag_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(surface_write_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
