@@ -317,9 +317,20 @@ def measure_surface(torch, psfs, slot, timed_graph, args):
     n = int(count.item())
     algo = 4 * V + 1 * V + 4 * n
     print(f"[bench] surface extraction {ms * 1e3:.2f} us ({n} surface voxels)", file=sys.stderr, flush=True)
-    return {"workload": "3x3x3 smoothing + threshold + surface list of the 128^3 posterior",
-            "us": ms * 1e3, "surface_voxels": n, "algorithmic_bytes": algo,
-            "achieved_GBs": algo / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": "3x3x3 smoothing + threshold + surface list of the 128^3 posterior",
+           "us": ms * 1e3, "surface_voxels": n, "algorithmic_bytes": algo,
+           "achieved_GBs": algo / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_cpu:
+        from oracle import surface as SO
+        p = post.cpu().numpy()
+        t0 = time.time()
+        nrep = 0
+        while nrep < 1 or (time.time() - t0 < 2.0 and nrep < 50):
+            SO.extract(p)
+            nrep += 1
+        out["cpu_oracle"] = {"us": 1e6 * (time.time() - t0) / nrep, "cores": 1, "kind": "oracle",
+                             "sample": f"{nrep} runs of the numpy FP64 oracle on the same posterior"}
+    return out
 
 
 def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
@@ -357,8 +368,32 @@ def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
     ms_f = timed_graph([fwd(d) for d in slots], reps, 3)
     ms_fb = timed_graph([fwdbwd(d) for d in slots], reps, 3)
     print(f"[bench] differentiable: fwd {ms_f * 1e3:.2f} us, fwd+bwd {ms_fb * 1e3:.2f} us", file=sys.stderr, flush=True)
-    return {"workload": "128^3 grid, 8 views 640x480, bilinear, BCE loss over the whole grid, cameras perturbed 1 %",
-            "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb, "ratio": ms_fb / ms_f, "target_ratio": 3.0}
+    fr = S.config_frame(4, 0)
+    npix, V = fr.npix, fr.grid.nvox
+    # algorithmic bytes: forward reads images + background (27 B/px) and labels
+    # (1 B/voxel) and writes logits (4 B/voxel); the backward reads logits and
+    # labels again, the images and background for the pixel chain, and writes
+    # the mean and variance gradients (24 B/px)
+    b_f = 27 * npix + 5 * V
+    b_fb = b_f + 51 * npix + 5 * V
+    out = {"workload": "128^3 grid, 8 views 640x480, bilinear, BCE loss over the whole grid, cameras perturbed 1 %",
+           "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb, "ratio": ms_fb / ms_f, "target_ratio": 3.0,
+           "roofline": {"bound": "hbm", "fwd_bytes": b_f, "fwd_bwd_bytes": b_fb,
+                        "fwd_frac": b_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "fwd_bwd_frac": b_fb / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    if not args.no_cpu:
+        from oracle import oracle as O
+        cams = S.perturb_cameras(fr.cams, seed=(4, 0))
+        lab = S.gt_occupancy(fr.grid, fr.body)
+        t0 = time.time()
+        nrep = 0
+        while nrep < 1 or (time.time() - t0 < args.cpu_seconds / 2 and nrep < 20):
+            O.grad(cams, fr.grid, fr.images, fr.mean, fr.var, lab)    # forward + loss + adjoint
+            nrep += 1
+        dt = time.time() - t0
+        out["cpu_oracle"] = {"ms_fwd_bwd": 1e3 * dt / nrep, "cores": O.threads(), "kind": "oracle",
+                             "sample": f"{nrep} full fwd+bwd frames (FP64 C oracle), {dt:.1f} s"}
+    return out
 
 
 def measure_batch(torch, psfs, S, args, nframes=64):

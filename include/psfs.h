@@ -202,6 +202,30 @@ int psfs_surface(psfs_plan *plan, const float *posterior_dev, float *smoothed_de
                  int32_t *surface_dev, int64_t capacity, int64_t *count_dev, void *workspace_dev,
                  size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------- voxel colour */
+
+/* Workspace of psfs_colour: one 8-byte depth-buffer entry per likelihood-map
+ * element (psfs_lmap_floats of them). 0 if cameras are unset. */
+size_t psfs_colour_workspace_bytes(const psfs_plan *plan);
+
+/* Colour of listed voxels from the views that see them (the paper's colour
+ * rendering of the reconstructed voxels, Sec. 3.1.1 and Sec. 3.3.3; its rule
+ * is not given, this one is): each voxel centre is projected into every view
+ * with the nearest-pixel rule of psfs_fuse; at every pixel the listed voxel
+ * with the smallest depth (third row of P applied to the centre, FP32) is
+ * visible, an equal depth going to the earlier list entry; a voxel's colour is
+ * the mean RGB of the pixels where it is visible, over those views.
+ *   images_dev  n device pointers, u8 [H][W][3] (4-byte aligned)
+ *   voxels_dev  int32 linear indices (k*ny + j)*nx + i, `count` of them, e.g.
+ *               the psfs_surface list; entries outside the grid are seen by
+ *               no view
+ *   colour_dev  FP32 [count][3]: the mean colour, 0 for a voxel no view sees
+ *   views_dev   int32 [count]: the number of views in which it is visible
+ * Needs cameras and grid. count in [0, 2^31). */
+int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t *voxels_dev, int64_t count,
+                float *colour_dev, int32_t *views_dev, void *workspace_dev, size_t workspace_bytes,
+                void *stream);
+
 /* ---------------------------------------- differentiable variant (bilinear) */
 
 /* Workspace of psfs_diff_forward / psfs_diff_backward: likelihood maps,

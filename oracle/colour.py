@@ -47,7 +47,7 @@ def voxel_centres(grid, indices: np.ndarray) -> np.ndarray:
 
 
 def project(cam, X: np.ndarray):
-    """(pixel x, pixel y, depth c, in_view, ambiguous) of FP64 points X [n,3]."""
+    """(pixel x, pixel y, depth c, in_view, ambiguous, u + 1/2, v + 1/2) of FP64 points X [n,3]."""
     P = np.asarray(cam.P, dtype=np.float64).reshape(3, 4)
     Xh = np.concatenate([X, np.ones((len(X), 1))], axis=1)
     a, b, c = (Xh @ P.T).T
@@ -57,7 +57,7 @@ def project(cam, X: np.ndarray):
     fx, fy = np.floor(u), np.floor(v)
     ok = (c > 0) & (fx >= 0) & (fx < cam.width) & (fy >= 0) & (fy < cam.height)
     amb = ((u - fx) < EPS_PX) | ((fx + 1 - u) < EPS_PX) | ((v - fy) < EPS_PX) | ((fy + 1 - v) < EPS_PX)
-    return fx.astype(np.int64), fy.astype(np.int64), c, ok, amb & (c > 0)
+    return fx.astype(np.int64), fy.astype(np.int64), c, ok, amb & (c > 0), u, v
 
 
 def colour(cams: Sequence, grid, images: Sequence[np.ndarray], indices: np.ndarray):
@@ -69,7 +69,7 @@ def colour(cams: Sequence, grid, images: Sequence[np.ndarray], indices: np.ndarr
     views = np.zeros(n, dtype=np.int64)
     ambiguous = np.zeros(n, dtype=bool)
     for cam, img in zip(cams, images):
-        x, y, c, ok, amb = project(cam, X)
+        x, y, c, ok, amb, u, v = project(cam, X)
         W = int(cam.width)
         pix = y * W + x
         # winner per pixel: smallest depth, then smallest list position
@@ -82,15 +82,16 @@ def colour(cams: Sequence, grid, images: Sequence[np.ndarray], indices: np.ndarr
         for w in winners:
             sums[w] += img[y[w], x[w]].astype(np.float64)
             views[w] += 1
-        # rounding-sensitive voxels: own pixel near a boundary; another
-        # candidate near a boundary that could land on this pixel (any of the
-        # 3x3 pixels around its own); a depth near-tie at the pixel
+        # rounding-sensitive voxels: a projection near a pixel boundary, and
+        # every candidate at a pixel such a projection may leave or reach
+        # (floor(u +- eps) x floor(v +- eps)); a depth near-tie at a pixel
         ambiguous |= amb
         unsafe = set()
         for q in np.flatnonzero(amb):
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    unsafe.add((int(y[q]) + dy) * W + int(x[q]) + dx)
+            for px in {int(np.floor(u[q] - EPS_PX)), int(np.floor(u[q] + EPS_PX))}:
+                for py in {int(np.floor(v[q] - EPS_PX)), int(np.floor(v[q] + EPS_PX))}:
+                    if 0 <= px < W and 0 <= py < cam.height:
+                        unsafe.add(py * W + px)
         for q in cand:
             if int(pix[q]) in unsafe:
                 ambiguous[q] = True

@@ -71,6 +71,8 @@ SIGNATURES = {
     "psfs_reconstruct": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
     "psfs_pipeline_step": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, vp, vp]),
     "psfs_surface_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_colour_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_colour": (C.c_int, [vp, C.POINTER(vp), vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]),
     "psfs_surface": (C.c_int, [vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
     "psfs_threshold": (C.c_int, [vp, C.c_int64, C.c_float, vp, vp]),
     "psfs_diff_workspace_bytes": (C.c_size_t, [vp]),

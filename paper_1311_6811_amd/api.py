@@ -233,6 +233,26 @@ class Plan:
                                      ws.numel(), _stream()))
         return Surface(occ, smoothed, out, count, cap)
 
+    # ---------------------------------------------------- voxel colour
+    def colour_workspace_bytes(self) -> int:
+        return int(L.lib().psfs_colour_workspace_bytes(self._h))
+
+    def colour(self, images: Sequence[torch.Tensor], voxels: torch.Tensor, colour=None, views=None,
+               workspace=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Mean RGB of each listed voxel over the views where it is the nearest
+        listed voxel at its pixel, and the number of such views."""
+        ims = self._images(images)
+        n = int(voxels.numel())
+        colour = colour if colour is not None else torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        views = views if views is not None else torch.empty(n, dtype=torch.int32, device="cuda")
+        ws = workspace if workspace is not None else torch.empty(max(self.colour_workspace_bytes(), 8),
+                                                                 dtype=torch.uint8, device="cuda")
+        L.check(L.lib().psfs_colour(self._h, ims, _dev(voxels, torch.int32, "voxels") if n else None, n,
+                                    _dev(colour, torch.float32, "colour", (n, 3)) if n else None,
+                                    _dev(views, torch.int32, "views", (n,)) if n else None,
+                                    _dev(ws, torch.uint8, "workspace"), ws.numel(), _stream()))
+        return colour, views
+
     # ------------------------------------------- differentiable variant
     def diff_workspace_bytes(self) -> int:
         return int(L.lib().psfs_diff_workspace_bytes(self._h))

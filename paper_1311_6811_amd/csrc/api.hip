@@ -566,6 +566,57 @@ int psfs_surface(psfs_plan *plan, const float *posterior_dev, float *smoothed_de
     PSFS_GUARD_END
 }
 
+size_t psfs_colour_workspace_bytes(const psfs_plan *plan)
+{
+    if (!plan || plan->n < 0) return 0;
+    return static_cast<size_t>(map_floats(plan)) * sizeof(unsigned long long);
+}
+
+int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t *voxels_dev, int64_t count,
+                float *colour_dev, int32_t *views_dev, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_grid(plan);
+    if (rc) return rc;
+    if (count < 0 || count >= (int64_t(1) << 31)) return fail(PSFS_E_RANGE, "voxel count %lld out of range", static_cast<long long>(count));
+    if ((rc = check_images(plan, images_dev))) return rc;
+    if (count > 0) {
+        if (!voxels_dev || !aligned(voxels_dev, 4)) return fail(PSFS_E_ARG, "voxel list must be a 4-byte aligned device pointer");
+        if (!colour_dev || !aligned(colour_dev, 4)) return fail(PSFS_E_ARG, "colour output must be a 4-byte aligned device pointer");
+        if (!views_dev || !aligned(views_dev, 4)) return fail(PSFS_E_ARG, "view-count output must be a 4-byte aligned device pointer");
+    }
+    const size_t need = psfs_colour_workspace_bytes(plan);
+    if (need > 0 && (!workspace_dev || workspace_bytes < need || !aligned(workspace_dev, 8)))
+        return fail(PSFS_E_WORKSPACE, "colour workspace needs %zu bytes, 8-byte aligned (got %zu)", need, workspace_bytes);
+    if (count == 0) return PSFS_OK;
+    if ((rc = check_device())) return rc;
+    FuseArgs fa{};
+    fill_geometry(plan, PSFS_NEAREST, fa);
+    ColourArgs a{};
+    for (int k = 0; k < plan->n; ++k) {
+        a.view[k] = fa.view[k];
+        a.img[k] = images_dev[k];
+    }
+    a.list = voxels_dev;
+    a.nlist = count;
+    a.zbuf = static_cast<unsigned long long *>(workspace_dev);
+    a.zbuf_len = map_floats(plan);
+    a.sums = reinterpret_cast<uint32_t *>(colour_dev);
+    a.views = views_dev;
+    a.nvox = nvox(plan->grid);
+    a.n = plan->n;
+    a.nx = fa.nx;
+    a.ny = fa.ny;
+    a.ox = fa.ox;
+    a.oy = fa.oy;
+    a.oz = fa.oz;
+    a.h = fa.h;
+    hipError_t e = launch_colour(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "colour kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
 size_t psfs_diff_workspace_bytes(const psfs_plan *plan)
 {
     if (!plan || plan->n < 0 || !plan->has_grid) return 0;

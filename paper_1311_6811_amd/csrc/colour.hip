@@ -1,0 +1,130 @@
+// Voxel colouring (Sec. 3.1.1; Sec. 3.3.3 "Voxel Projection and Color
+// Computation"): the colour of every listed voxel (normally the surface list)
+// from the views that see it. Four launches:
+//   colour_clear_kernel  depth buffers to "empty", colour sums and view counts to 0
+//   depth_kernel         per (voxel, view): project as the fusion does and keep
+//                        the nearest voxel of every pixel with a 64-bit atomic
+//                        minimum of (depth bits << 32 | list position)
+//   colour_kernel        per (voxel, view): a voxel that holds its pixel adds
+//                        the pixel's RGB to its sums and counts the view
+//   colour_final_kernel  per voxel: sums / count (in place), 0 if unseen
+// Depths are positive FP32, whose bit patterns order like the values, so the
+// minimum key is the nearest voxel and, on equal depth, the earlier one in the
+// list. The sums are integers, so the result does not depend on the order of
+// the atomics.
+#include "kernels_common.h"
+
+namespace psfs {
+namespace {
+
+using namespace dev;
+
+constexpr unsigned long long kEmpty = ~0ull;
+
+// Pixel offset (within the view's buffer) and depth of list entry q in view g,
+// or false when the view does not see it. Same FP32 arithmetic as the
+// fusion's checked path, so both pick the same pixel.
+__device__ __forceinline__ bool locate(const ColourArgs &a, const ViewGeom &g, int64_t vox, uint32_t &pix,
+                                       float &depth)
+{
+    if (vox < 0 || vox >= a.nvox) return false;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    const int k = static_cast<int>(vox / plane);
+    const int64_t rem = vox - static_cast<int64_t>(k) * plane;
+    const int j = static_cast<int>(rem / a.nx), i = static_cast<int>(rem - static_cast<int64_t>(j) * a.nx);
+    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
+    const float Z = a.oz + a.h * (static_cast<float>(k) + 0.5f);
+    const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+    const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+    const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+    const float c = fmaf(g.P[10], Z, cx);
+    const float r = __builtin_amdgcn_rcpf(c);
+    const int x = static_cast<int>(floorf(fmaf(g.P[2], Z, ax) * r));
+    const int y = static_cast<int>(floorf(fmaf(g.P[6], Z, bx) * r));
+    if (!(c > 0.0f) || static_cast<uint32_t>(x) >= static_cast<uint32_t>(g.W) ||
+        static_cast<uint32_t>(y) >= static_cast<uint32_t>(g.H))
+        return false;
+    pix = static_cast<uint32_t>(y) * static_cast<uint32_t>(g.W) + static_cast<uint32_t>(x);
+    depth = c;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void colour_clear_kernel(ColourArgs a)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < a.zbuf_len; t += stride)
+        a.zbuf[t] = kEmpty;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nlist; t += stride) {
+        a.sums[3 * t] = a.sums[3 * t + 1] = a.sums[3 * t + 2] = 0u;
+        a.views[t] = 0;
+    }
+}
+
+// grid (ceil(nlist / 256), views)
+__global__ __launch_bounds__(256) void depth_kernel(ColourArgs a)
+{
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.nlist) return;
+    const ViewGeom &g = a.view[blockIdx.y];
+    uint32_t pix;
+    float depth;
+    if (!locate(a, g, a.list[q], pix, depth)) return;
+    const unsigned long long key =
+        (static_cast<unsigned long long>(__float_as_uint(depth)) << 32) | static_cast<unsigned long long>(q);
+    atomicMin(a.zbuf + g.map_off + pix, key);
+}
+
+__global__ __launch_bounds__(256) void colour_kernel(ColourArgs a)
+{
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.nlist) return;
+    const int v = static_cast<int>(blockIdx.y);
+    const ViewGeom &g = a.view[v];
+    uint32_t pix;
+    float depth;
+    if (!locate(a, g, a.list[q], pix, depth)) return;
+    const unsigned long long key =
+        (static_cast<unsigned long long>(__float_as_uint(depth)) << 32) | static_cast<unsigned long long>(q);
+    if (a.zbuf[g.map_off + pix] != key) return;
+    const uint8_t *p = a.img[v] + 3 * static_cast<int64_t>(pix);
+    atomicAdd(a.sums + 3 * q, static_cast<uint32_t>(p[0]));
+    atomicAdd(a.sums + 3 * q + 1, static_cast<uint32_t>(p[1]));
+    atomicAdd(a.sums + 3 * q + 2, static_cast<uint32_t>(p[2]));
+    atomicAdd(a.views + q, 1);
+}
+
+__global__ __launch_bounds__(256) void colour_final_kernel(ColourArgs a)
+{
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.nlist) return;
+    const int n = a.views[q];
+    float *col = reinterpret_cast<float *>(a.sums + 3 * q);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const uint32_t s = a.sums[3 * q + ch];
+        col[ch] = n > 0 ? static_cast<float>(s) / static_cast<float>(n) : 0.0f;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_colour(const ColourArgs &a, hipStream_t s)
+{
+    const int64_t fill = a.zbuf_len > a.nlist ? a.zbuf_len : a.nlist;
+    int64_t cb = (fill + 255) / 256;
+    if (cb > 4096) cb = 4096;
+    if (cb < 1) cb = 1;
+    hipLaunchKernelGGL(colour_clear_kernel, dim3(static_cast<unsigned>(cb)), dim3(256), 0, s, a);
+    if (a.nlist > 0) {
+        const unsigned qb = static_cast<unsigned>((a.nlist + 255) / 256);
+        if (a.n > 0) {
+            hipLaunchKernelGGL(depth_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(colour_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
+        }
+        hipLaunchKernelGGL(colour_final_kernel, dim3(qb), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace psfs

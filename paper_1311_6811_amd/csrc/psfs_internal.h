@@ -147,6 +147,21 @@ struct SurfArgs {
     float tau;
 };
 
+// Voxel colouring of a list of voxels (depth-buffer visibility).
+struct ColourArgs {
+    ViewGeom view[kMaxViews];           // nearest-pixel P (pre-offset), W, H; map_off = offset in zbuf
+    const uint8_t *img[kMaxViews];      // [H][W][3]
+    const int32_t *list;                // linear voxel indices
+    int64_t nlist;
+    unsigned long long *zbuf;           // workspace: (depth bits << 32 | position) per pixel
+    int64_t zbuf_len;
+    uint32_t *sums;                     // the colour output [nlist][3]: integer sums, then FP32 means
+    int32_t *views;                     // [nlist]: number of views that see the voxel
+    int64_t nvox;
+    int32_t n, nx, ny;
+    float ox, oy, oz, h;
+};
+
 struct TileCfg {
     int tx, ty, kz;                     // x-by-y lanes per workgroup, z voxels per lane
 };
@@ -171,6 +186,7 @@ int batch_fuse_occupancy(int tile, int sampling);
 hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid, int fuse_grid, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 int64_t surface_blocks(int64_t nvox);
+hipError_t launch_colour(const ColourArgs &a, hipStream_t s);
 hipError_t launch_surface(const SurfArgs &a, hipStream_t s);   // a.nvox == 0: writes count 0 only
 
 }  // namespace psfs

@@ -189,6 +189,29 @@ def test_surface_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_colour_validation_without_device(lib):
+    h = _plan(lib)
+    fake = C.c_void_p(0x100000)
+    imgs = L.ptr_array([0x100000, 0x100000])
+    assert lib.psfs_colour_workspace_bytes(h) == 0
+    assert lib.psfs_colour(h, imgs, fake, 10, fake, fake, fake, 4096, None) == -3        # cameras missing
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_colour(h, imgs, fake, 10, fake, fake, fake, 4096, None) == -3        # grid missing
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    need = lib.psfs_colour_workspace_bytes(h)
+    assert need == 8 * 128                                   # 8 B per element of the 128-float map layout
+    assert lib.psfs_colour(h, imgs, fake, -1, fake, fake, fake, need, None) == -2
+    assert lib.psfs_colour(h, None, fake, 10, fake, fake, fake, need, None) == -1
+    assert lib.psfs_colour(h, imgs, None, 10, fake, fake, fake, need, None) == -1
+    assert lib.psfs_colour(h, imgs, fake, 10, None, fake, fake, need, None) == -1
+    assert lib.psfs_colour(h, imgs, fake, 10, fake, None, fake, need, None) == -1
+    assert lib.psfs_colour(h, imgs, fake, 10, fake, fake, fake, need - 8, None) == -4
+    assert lib.psfs_colour(h, imgs, fake, 0, None, None, fake, need, None) == 0         # empty list: no-op
+    lib.psfs_plan_destroy(h)
+
+
 def test_empty_work_is_a_no_op_without_device(lib):
     h = _plan(lib)
     assert lib.psfs_set_cameras(h, 0, None) == 0

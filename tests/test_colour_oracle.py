@@ -24,8 +24,8 @@ def test_hand_case_nearest_voxel_on_a_ray_wins():
     idx = np.arange(4)
     col, views, amb = CO.colour([cam0, cam1], grid, [im0, im1], idx)
     assert views.tolist() == [1, 1, 1, 2]                  # only the voxel at x = 0.3125 wins in camera 0
-    x1, y1, _, ok1, _ = CO.project(cam1, CO.voxel_centres(grid, idx))
-    x0, y0, _, ok0, _ = CO.project(cam0, CO.voxel_centres(grid, idx))
+    x1, y1, _, ok1, _, _, _ = CO.project(cam1, CO.voxel_centres(grid, idx))
+    x0, y0, _, ok0, _, _, _ = CO.project(cam0, CO.voxel_centres(grid, idx))
     assert ok0.all() and ok1.all() and len(set(zip(x1, y1))) == 4 and len(set(zip(x0, y0))) == 1
     for v in range(3):
         assert np.array_equal(col[v], im1[y1[v], x1[v]].astype(np.float64))
@@ -83,7 +83,7 @@ def test_one_winner_per_pixel():
     X = CO.voxel_centres(grid, idx)
     distinct = 0
     for cam in cams:
-        x, y, _, ok, _ = CO.project(cam, X)
+        x, y, _, ok, _, _, _ = CO.project(cam, X)
         distinct += len(set(zip(x[ok].tolist(), y[ok].tolist())))
     assert views.sum() == distinct
     assert np.all(col == 0)
