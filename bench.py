@@ -243,6 +243,7 @@ def main():
     traffic = pipe_traffic() if graph else None
 
     surface = measure_surface(torch, psfs, slots[0], timed_graph, args)
+    colour = measure_colour(torch, psfs, slots[0], frames[0], timed_graph, args)
     diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
 
@@ -292,6 +293,7 @@ def main():
                           "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "parity_max_abs_err": max_err,
         "surface": surface,
+        "colour": colour,
         "fwd_bwd": diff,
         "batch": batch,
         "cpu_baseline": cpu,
@@ -330,6 +332,37 @@ def measure_surface(torch, psfs, slot, timed_graph, args):
             nrep += 1
         out["cpu_oracle"] = {"us": 1e6 * (time.time() - t0) / nrep, "cores": 1, "kind": "oracle",
                              "sample": f"{nrep} runs of the numpy FP64 oracle on the same posterior"}
+    return out
+
+
+def measure_colour(torch, psfs, slot, frame, timed_graph, args):
+    """Colour of the headline frame's surface voxels from its 8 views (four
+    launches), replayed from a HIP graph."""
+    plan, post, ims = slot["plan"], slot["post"], slot["ims"]
+    idx = plan.surface(post).indices().contiguous()
+    n = int(idx.numel())
+    colour = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    views = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(plan.colour_workspace_bytes(), 8), dtype=torch.uint8, device="cuda")
+
+    def f():
+        plan.colour(ims, idx, colour=colour, views=views, workspace=ws)
+
+    ms = timed_graph([f], max(20, args.steps // 10), 5)
+    npix = frame.npix
+    # algorithmic bytes: the depth buffer cleared (8 B per pixel of every view)
+    # and the list, its pixels and its outputs (small next to the buffer)
+    algo = 8 * npix + n * (4 + 12 + 4)
+    print(f"[bench] voxel colour {ms * 1e3:.2f} us ({n} voxels)", file=sys.stderr, flush=True)
+    out = {"workload": "colour of the surface voxels of the 128^3 x 8-view frame", "us": ms * 1e3, "voxels": n,
+           "algorithmic_bytes": algo, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_cpu:
+        from oracle import colour as CO
+        li = idx.cpu().numpy()
+        t0 = time.time()
+        CO.colour(frame.cams, frame.grid, frame.images, li)
+        out["cpu_oracle"] = {"us": 1e6 * (time.time() - t0), "cores": 1, "kind": "oracle",
+                             "sample": "one run of the numpy FP64 oracle on the same list"}
     return out
 
 
