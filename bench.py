@@ -37,9 +37,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E spec
 # those change, traffic is reported as null until the counters are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "2af0b9272a5d95b42d1b1ad215cf8343dacd0e61f2f1b3c50a4d4655294b48b4",
-                 "fetch_kib": 38281.3, "fetch_scale": 2.0, "write_kib": 20049.1, "write_scale": 1.0,
-                 "l2_hit_rate": 0.655}
+PIPE_COUNTERS = {"sources_sha256": "23219ffcca2982129233707324f1635d2184e0c747244a758960ba3d9a65cf2f",
+                 "fetch_kib": 38268.1, "fetch_scale": 2.0, "write_kib": 19904.0, "write_scale": 1.0,
+                 "l2_hit_rate": 0.636}
 
 
 def sources_sha256() -> str:
