@@ -38,13 +38,15 @@ __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
 template <int TX, int TY, int KZ, int SAMPLING>
 __device__ __forceinline__ void fuse_tile(const FuseArgs &a, int64_t b)
 {
-    const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
-    const int64_t ntile = static_cast<int64_t>(ntx) * nty;
-    const int64_t zc = b / ntile;
-    const int t = static_cast<int>(b - zc * ntile);
-    const int tyi = t / ntx, txi = t - tyi * ntx;
-    const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
-    const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
+    // tile counts are below nx*ny*nz < 2^31: 32-bit arithmetic
+    const uint32_t ntx = static_cast<uint32_t>((a.nx + TX - 1) / TX), nty = static_cast<uint32_t>((a.ny + TY - 1) / TY);
+    const uint32_t ntile = ntx * nty;
+    const uint32_t bb = static_cast<uint32_t>(b);
+    const uint32_t zc = bb / ntile;
+    const uint32_t t = bb - zc * ntile;
+    const uint32_t tyi = t / ntx, txi = t - tyi * ntx;
+    const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
+    const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
     const int k0 = static_cast<int>(zc) * KZ;
     const GridDesc gd{a.nx, a.ny, a.nz, a.ox, a.oy, a.oz, a.h};
     fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return a.view[v]; }, a.n, a.lmap, gd, i, j, k0,

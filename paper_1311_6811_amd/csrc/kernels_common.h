@@ -259,8 +259,9 @@ __device__ __forceinline__ uint32_t wave_inside_mask(const Views &views, int n, 
         if (v < n) {
             const ViewGeom &g = views(v);
             const float c = fmaf(g.P[10], Z, fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11])));
-            const float u = fmaf(g.P[2], Z, fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]))) / c;
-            const float w = fmaf(g.P[6], Z, fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]))) / c;
+            const float rc = __builtin_amdgcn_rcpf(c);      // ~1 ulp: far inside the margin
+            const float u = fmaf(g.P[2], Z, fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]))) * rc;
+            const float w = fmaf(g.P[6], Z, fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]))) * rc;
             ok = c > 0.0f && u >= kMargin && u <= static_cast<float>(g.W) - kMargin && w >= kMargin &&
                  w <= static_cast<float>(g.H) - kMargin;
         }
@@ -396,11 +397,11 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
     }
 
     if (i >= a.nx || j >= a.ny) return;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    int64_t idx = (static_cast<int64_t>(k0) * a.ny + j) * a.nx + i;
 #pragma unroll
-    for (int kk = 0; kk < KZ; ++kk) {
-        const int k = k0 + kk;
-        if (k < a.nz) {
-            const int64_t idx = (static_cast<int64_t>(k) * a.ny + j) * a.nx + i;
+    for (int kk = 0; kk < KZ; ++kk, idx += plane) {
+        if (k0 + kk < a.nz) {
             const float p = sigmoid_fast(L[kk]);
             post[idx] = p;
             if (occ) occ[idx] = p > tau ? 1 : 0;
