@@ -50,6 +50,7 @@ extern "C" {
 
 #define PSFS_VERSION 1
 #define PSFS_MAX_VIEWS 16
+#define PSFS_FG_BINS 4096       /* colour bins of the learned foreground model */
 
 enum psfs_status {
     PSFS_OK = 0,
@@ -172,6 +173,34 @@ int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float 
  * tau in [0,1]; nvox >= 0. */
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,
                    void *stream);
+
+/* ------------------------------------------ foreground model after frame 1 */
+
+/* Eq. 1-2 take the foreground colour density as uniform (log_u) because the
+ * foreground is unknown for the first frame (Sec. 2.2.2). For later frames a
+ * learned model can replace it (the paper implies one, without describing
+ * it; this is the reading taken): a histogram of PSFS_FG_BINS colour bins
+ * (bin = (R >> 4) * 256 + (G >> 4) * 16 + (B >> 4)) of the foreground pixels
+ * of a frame, pooled over the views, Laplace-smoothed into the density of one
+ * colour value, log((count + 1) / ((N + 4096) * 4096)) per bin.
+ *   images_dev       n device pointers, u8 [H][W][3] (the frame to learn from)
+ *   masks_dev        host array of n nullable device pointers to u8 [H][W]
+ *                    (nonzero = foreground), or NULL; a view without a mask
+ *                    takes its foreground pixels from lmap_dev: log(2*SLM) > 0
+ *                    (SLM > 1/2), maps in the psfs_lmap_* layout
+ *   log_density_dev  FP32 [PSFS_FG_BINS] output
+ *   workspace        PSFS_FG_BINS * 4 bytes (the counts)
+ * Needs cameras. */
+int psfs_foreground_model(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *const *masks_dev,
+                          const float *lmap_dev, float *log_density_dev, void *workspace_dev,
+                          size_t workspace_bytes, void *stream);
+
+/* Use a learned model (FP32 [PSFS_FG_BINS] log densities on the device,
+ * borrowed until replaced) in psfs_likelihood, psfs_reconstruct and
+ * psfs_pipeline_step: SLM = F(I) / (F(I) + N(I | mu, var)) with
+ * F(I) = exp(log_density[bin(I)]) in place of u. NULL restores the uniform
+ * density. The differentiable variant and batches keep the uniform density. */
+int psfs_set_foreground(psfs_plan *plan, const float *log_density_dev);
 
 /* ------------------------------------------- smoothing and surface voxels */
 

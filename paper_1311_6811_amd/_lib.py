@@ -12,6 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpsfs.so")
 
 MAX_VIEWS = 16
+FG_BINS = 4096
 NEAREST, BILINEAR = 0, 1
 
 STATUS = {
@@ -72,6 +73,8 @@ SIGNATURES = {
     "psfs_pipeline_step": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, vp, vp]),
     "psfs_surface_workspace_bytes": (C.c_size_t, [vp]),
     "psfs_colour_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_foreground_model": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
+    "psfs_set_foreground": (C.c_int, [vp, vp]),
     "psfs_colour": (C.c_int, [vp, C.POINTER(vp), vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]),
     "psfs_surface": (C.c_int, [vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
     "psfs_threshold": (C.c_int, [vp, C.c_int64, C.c_float, vp, vp]),

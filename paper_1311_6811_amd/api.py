@@ -233,6 +233,32 @@ class Plan:
                                      ws.numel(), _stream()))
         return Surface(occ, smoothed, out, count, cap)
 
+    # ------------------------------------- foreground model after frame 1
+    def foreground_model(self, images: Sequence[torch.Tensor], masks=None, lmap: Optional[torch.Tensor] = None,
+                         out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Log density per colour bin learned from the foreground pixels of a
+        frame: `masks` (u8 [H][W] per view, nonzero = foreground; None entries
+        or masks=None use lmap > 0, i.e. SLM > 1/2 in that frame's maps)."""
+        ims = self._images(images)
+        mp = None
+        if masks is not None:
+            if len(masks) != self.n:
+                raise ValueError(f"expected {self.n} masks, got {len(masks)}")
+            mp = L.ptr_array([_dev(m, torch.uint8, f"masks[{k}]", (c.height, c.width)) if m is not None else None
+                              for k, (m, c) in enumerate(zip(masks, self.cams))])
+        out = out if out is not None else torch.empty(L.FG_BINS, dtype=torch.float32, device="cuda")
+        ws = workspace if workspace is not None else torch.empty(4 * L.FG_BINS, dtype=torch.uint8, device="cuda")
+        L.check(L.lib().psfs_foreground_model(self._h, ims, mp, _dev(lmap, torch.float32, "lmap") if lmap is not None else None,
+                                              _dev(out, torch.float32, "log_density", (L.FG_BINS,)),
+                                              _dev(ws, torch.uint8, "workspace"), ws.numel(), _stream()))
+        return out
+
+    def set_foreground(self, log_density: Optional[torch.Tensor]) -> None:
+        """Use a learned foreground model in the likelihood maps (None: uniform)."""
+        ptr = _dev(log_density, torch.float32, "log_density", (L.FG_BINS,)) if log_density is not None else None
+        L.check(L.lib().psfs_set_foreground(self._h, ptr))
+        self._keep["fg"] = log_density
+
     # ---------------------------------------------------- voxel colour
     def colour_workspace_bytes(self) -> int:
         return int(L.lib().psfs_colour_workspace_bytes(self._h))

@@ -19,6 +19,7 @@ struct psfs_plan {
     psfs_params params{};
     const float *mean[PSFS_MAX_VIEWS] = {};
     const float *var[PSFS_MAX_VIEWS] = {};
+    const float *fg = nullptr;                      // learned foreground model (log density per bin)
     int tile = -1;
 };
 
@@ -146,11 +147,13 @@ int check_images(const psfs_plan *p, const uint8_t *const *images)
 
 // Likelihood-kernel arguments for the views of p; returns the largest view's
 // pixel count.
-int64_t fill_slm(const psfs_plan *p, const uint8_t *const *images, float *lmap, SlmArgs &a)
+int64_t fill_slm(const psfs_plan *p, const uint8_t *const *images, float *lmap, SlmArgs &a, bool use_fg = true)
 {
     a.n = p->n;
     a.lmap = lmap;
-    a.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(p->params.log_u));
+    a.fg = use_fg ? p->fg : nullptr;
+    a.k0 = a.fg ? static_cast<float>(-1.5 * std::log(2.0 * M_PI))
+                : static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(p->params.log_u));
     int64_t max_np = 0;
     for (int k = 0; k < p->n; ++k) {
         const int64_t np = static_cast<int64_t>(p->cams[k].width) * p->cams[k].height;
@@ -160,13 +163,14 @@ int64_t fill_slm(const psfs_plan *p, const uint8_t *const *images, float *lmap, 
     return max_np;
 }
 
-int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *lmap, hipStream_t s)
+int enqueue_likelihood(const psfs_plan *p, const uint8_t *const *images, float *lmap, hipStream_t s,
+                       bool use_fg = true)
 {
     if (p->n == 0) return PSFS_OK;
     int rc = check_device();
     if (rc) return rc;
     SlmArgs a{};
-    const int64_t max_np = fill_slm(p, images, lmap, a);
+    const int64_t max_np = fill_slm(p, images, lmap, a, use_fg);
     hipError_t e = launch_slm(a, max_np, s);
     if (e != hipSuccess) return hip_fail(e, "likelihood kernel launch");
     return PSFS_OK;
@@ -617,6 +621,49 @@ int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t
     PSFS_GUARD_END
 }
 
+int psfs_foreground_model(psfs_plan *plan, const uint8_t *const *images_dev, const uint8_t *const *masks_dev,
+                          const float *lmap_dev, float *log_density_dev, void *workspace_dev, size_t workspace_bytes,
+                          void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_cameras(plan);
+    if (rc) return rc;
+    if ((rc = check_images(plan, images_dev))) return rc;
+    if (!log_density_dev || !aligned(log_density_dev, 4))
+        return fail(PSFS_E_ARG, "log_density must be a 4-byte aligned device pointer");
+    bool need_maps = !masks_dev;
+    for (int k = 0; masks_dev && k < plan->n; ++k) need_maps = need_maps || !masks_dev[k];
+    if (need_maps && plan->n > 0 && (!lmap_dev || !aligned(lmap_dev, 4)))
+        return fail(PSFS_E_ARG, "lmap is needed for views without a mask");
+    if (!workspace_dev || workspace_bytes < PSFS_FG_BINS * sizeof(uint32_t) || !aligned(workspace_dev, 4))
+        return fail(PSFS_E_WORKSPACE, "foreground workspace needs %zu bytes", static_cast<size_t>(PSFS_FG_BINS * sizeof(uint32_t)));
+    if ((rc = check_device())) return rc;
+    FgArgs a{};
+    a.n = plan->n;
+    int64_t max_np = 0;
+    for (int k = 0; k < plan->n; ++k) {
+        const int64_t np = static_cast<int64_t>(plan->cams[k].width) * plan->cams[k].height;
+        a.view[k] = SlmView{images_dev[k], nullptr, nullptr, np, map_offset(plan, k)};
+        a.mask[k] = masks_dev ? masks_dev[k] : nullptr;
+        if (np > max_np) max_np = np;
+    }
+    a.lmap = lmap_dev;
+    a.counts = static_cast<uint32_t *>(workspace_dev);
+    a.logd = log_density_dev;
+    hipError_t e = launch_foreground(a, max_np, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "foreground model kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
+int psfs_set_foreground(psfs_plan *plan, const float *log_density_dev)
+{
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (log_density_dev && !aligned(log_density_dev, 4)) return fail(PSFS_E_ARG, "log_density must be 4-byte aligned");
+    plan->fg = log_density_dev;
+    return PSFS_OK;
+}
+
 size_t psfs_diff_workspace_bytes(const psfs_plan *plan)
 {
     if (!plan || plan->n < 0 || !plan->has_grid) return 0;
@@ -637,7 +684,9 @@ int psfs_diff_forward(psfs_plan *plan, const uint8_t *const *images_dev, const u
     if ((rc = check_device())) return rc;
     a.logits = logits_dev;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((rc = enqueue_likelihood(plan, images_dev, const_cast<float *>(a.lmap), s))) return rc;
+    // the differentiable variant keeps the uniform foreground density (the
+    // pixel chain differentiates that form)
+    if ((rc = enqueue_likelihood(plan, images_dev, const_cast<float *>(a.lmap), s, false))) return rc;
     hipError_t e = launch_diff_forward(a, loss_dev, s);
     if (e != hipSuccess) return hip_fail(e, "differentiable forward launch");
     return PSFS_OK;

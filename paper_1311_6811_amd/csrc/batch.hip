@@ -65,9 +65,9 @@ __global__ __launch_bounds__(256) void batch_slm_kernel(BatchArgs a)
             const int64_t p0 = (c - bv.chunk0) * kChunkPixels + wave * kWavePixels;
             float *out = a.lmap + bv.g.map_off;
             if (p0 + kWavePixels <= bv.npix)
-                slm_wave(bv.img, bv.mean, bv.var, out, p0, a.k0, stage[wave]);
+                slm_wave(bv.img, bv.mean, bv.var, out, p0, a.k0, stage[wave], nullptr);
             else if (p0 < bv.npix)
-                slm_wave_tail(bv.img, bv.mean, bv.var, out, p0, bv.npix, a.k0);
+                slm_wave_tail(bv.img, bv.mean, bv.var, out, p0, bv.npix, a.k0, nullptr);
         }
     }
 }

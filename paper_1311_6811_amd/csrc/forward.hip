@@ -26,9 +26,9 @@ __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
     const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * kWavePixels;
     float *out = a.lmap + sv.map_off;
     if (p0 + kWavePixels <= sv.npix)
-        slm_wave(sv.img, sv.mean, sv.var, out, p0, a.k0, stage[wave]);
+        slm_wave(sv.img, sv.mean, sv.var, out, p0, a.k0, stage[wave], a.fg);
     else if (p0 < sv.npix)
-        slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, a.k0);
+        slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, a.k0, a.fg);
 }
 
 // Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,
@@ -92,9 +92,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_kernel(SlmArgs s, FuseArgs f, Pi
         const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * 4 + wave) * kWavePixels;
         float *out = s.lmap + sv.map_off;
         if (p0 + kWavePixels <= sv.npix)
-            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave]);
+            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave], s.fg);
         else if (p0 < sv.npix)
-            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0);
+            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0, s.fg);
     } else {
         const int fr = round - p.slm_rounds;
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + fr;

@@ -72,18 +72,42 @@ struct Quad {
     f32x4 m[3], v[3];
 };
 
-__device__ __forceinline__ f32x4 quad_log2slm(const Quad &q, float k0)
+__device__ __forceinline__ f32x4 quad_log2slm(const Quad &q, f32x4 k0)
 {
     f32x4 r;
     r.x = log2slm(byte_of(q.w[0], 0), byte_of(q.w[0], 1), byte_of(q.w[0], 2), q.m[0].x, q.m[0].y, q.m[0].z,
-                  q.v[0].x, q.v[0].y, q.v[0].z, k0);
+                  q.v[0].x, q.v[0].y, q.v[0].z, k0.x);
     r.y = log2slm(byte_of(q.w[0], 3), byte_of(q.w[1], 0), byte_of(q.w[1], 1), q.m[0].w, q.m[1].x, q.m[1].y,
-                  q.v[0].w, q.v[1].x, q.v[1].y, k0);
+                  q.v[0].w, q.v[1].x, q.v[1].y, k0.y);
     r.z = log2slm(byte_of(q.w[1], 2), byte_of(q.w[1], 3), byte_of(q.w[2], 0), q.m[1].z, q.m[1].w, q.m[2].x,
-                  q.v[1].z, q.v[1].w, q.v[2].x, k0);
+                  q.v[1].z, q.v[1].w, q.v[2].x, k0.z);
     r.w = log2slm(byte_of(q.w[2], 1), byte_of(q.w[2], 2), byte_of(q.w[2], 3), q.m[2].y, q.m[2].z, q.m[2].w,
-                  q.v[2].y, q.v[2].z, q.v[2].w, k0);
+                  q.v[2].y, q.v[2].z, q.v[2].w, k0.w);
     return r;
+}
+
+// Colour bin of a pixel in the learned foreground model: 16 levels per
+// channel, bin = (R >> 4) * 256 + (G >> 4) * 16 + (B >> 4).
+__device__ __forceinline__ uint32_t colour_bin(uint32_t r, uint32_t g, uint32_t b)
+{
+    return ((r >> 4) << 8) | ((g >> 4) << 4) | (b >> 4);
+}
+
+__device__ __forceinline__ uint32_t byte_u(uint32_t w, int b) { return (w >> (8 * b)) & 0xffu; }
+
+// Per-pixel constant of d for a quad: k0 with the uniform foreground density
+// (k0 = -1.5 log 2pi - log u); with a learned model (fg = log density per
+// colour bin), k0 - fg[bin] where k0 = -1.5 log 2pi.
+__device__ __forceinline__ f32x4 quad_k0(const Quad &q, float k0, const float *fg)
+{
+    f32x4 k{k0, k0, k0, k0};
+    if (fg) {
+        k.x -= fg[colour_bin(byte_u(q.w[0], 0), byte_u(q.w[0], 1), byte_u(q.w[0], 2))];
+        k.y -= fg[colour_bin(byte_u(q.w[0], 3), byte_u(q.w[1], 0), byte_u(q.w[1], 1))];
+        k.z -= fg[colour_bin(byte_u(q.w[1], 2), byte_u(q.w[1], 3), byte_u(q.w[2], 0))];
+        k.w -= fg[colour_bin(byte_u(q.w[2], 1), byte_u(q.w[2], 2), byte_u(q.w[2], 3))];
+    }
+    return k;
 }
 
 constexpr int kWavePixels = 256;        // pixels per wave in the likelihood kernels
@@ -112,7 +136,7 @@ __device__ __forceinline__ void wave_lds_sync()
 // per-quad load (48 B apart per lane) touches three times the cache lines per
 // instruction and measured ~40 % slower.
 __device__ __forceinline__ void slm_wave(const uint8_t *img, const float *mean, const float *var, float *out,
-                                         int64_t p0, float k0, SlmStage &st)
+                                         int64_t p0, float k0, SlmStage &st, const float *fg)
 {
     const int lane = static_cast<int>(threadIdx.x & 63);
     const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
@@ -145,13 +169,13 @@ __device__ __forceinline__ void slm_wave(const uint8_t *img, const float *mean, 
 #pragma unroll
     for (int r = 0; r < 3; ++r) q.v[r] = st.f[3 * lane + r];
     wave_lds_sync();
-    *reinterpret_cast<f32x4 *>(out + p0 + 4 * lane) = quad_log2slm(q, k0);
+    *reinterpret_cast<f32x4 *>(out + p0 + 4 * lane) = quad_log2slm(q, quad_k0(q, k0, fg));
 }
 
 // The same for a wave whose span [p0, p0 + 256) reaches past npix: lane l
 // converts its quad p0 + 4l directly, or the pixels of it below npix.
 __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *mean, const float *var, float *out,
-                                              int64_t p0, int64_t npix, float k0)
+                                              int64_t p0, int64_t npix, float k0, const float *fg)
 {
     const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
     if (p + 4 <= npix) {
@@ -165,12 +189,13 @@ __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *m
             q.m[r] = mp[r];
             q.v[r] = vp[r];
         }
-        *reinterpret_cast<f32x4 *>(out + p) = quad_log2slm(q, k0);
+        *reinterpret_cast<f32x4 *>(out + p) = quad_log2slm(q, quad_k0(q, k0, fg));
     } else {
         for (int64_t t = p; t < npix; ++t) {
             const uint8_t *I = img + 3 * t;
             const float *mm = mean + 3 * t, *vv = var + 3 * t;
-            out[t] = log2slm(I[0], I[1], I[2], mm[0], mm[1], mm[2], vv[0], vv[1], vv[2], k0);
+            const float kt = fg ? k0 - fg[colour_bin(I[0], I[1], I[2])] : k0;
+            out[t] = log2slm(I[0], I[1], I[2], mm[0], mm[1], mm[2], vv[0], vv[1], vv[2], kt);
         }
     }
 }

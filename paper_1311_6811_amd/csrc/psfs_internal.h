@@ -26,7 +26,19 @@ struct SlmView {
 struct SlmArgs {
     SlmView view[kMaxViews];
     float *lmap;
-    float k0;                           // -1.5*log(2*pi) - log_u
+    const float *fg;                    // nullable: log density per colour bin of a learned foreground model
+    float k0;                           // -1.5*log(2*pi) - log_u; -1.5*log(2*pi) with fg
+    int32_t n;
+};
+
+// Learned foreground colour model: histogram of the marked pixels of all
+// views, then the log density per colour bin.
+struct FgArgs {
+    SlmView view[kMaxViews];            // img, npix and map_off are used
+    const uint8_t *mask[kMaxViews];     // nullable per view: nonzero = foreground; else lmap > 0
+    const float *lmap;
+    uint32_t *counts;                   // [4096]
+    float *logd;                        // [4096]
     int32_t n;
 };
 
@@ -187,6 +199,7 @@ hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 int64_t surface_blocks(int64_t nvox);
 hipError_t launch_colour(const ColourArgs &a, hipStream_t s);
+hipError_t launch_foreground(const FgArgs &a, int64_t max_npix, hipStream_t s);
 hipError_t launch_surface(const SurfArgs &a, hipStream_t s);   // a.nvox == 0: writes count 0 only
 
 }  // namespace psfs

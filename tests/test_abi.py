@@ -212,6 +212,25 @@ def test_colour_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_foreground_validation_without_device(lib):
+    h = _plan(lib)
+    fake = C.c_void_p(0x100000)
+    imgs = L.ptr_array([0x100000, 0x100000])
+    assert lib.psfs_foreground_model(h, imgs, None, fake, fake, fake, 16384, None) == -3     # cameras missing
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_foreground_model(h, None, None, fake, fake, fake, 16384, None) == -1
+    assert lib.psfs_foreground_model(h, imgs, None, fake, None, fake, 16384, None) == -1     # no output
+    assert lib.psfs_foreground_model(h, imgs, None, None, fake, fake, 16384, None) == -1     # no masks, no maps
+    masks = L.ptr_array([0x100000, 0])
+    assert lib.psfs_foreground_model(h, imgs, masks, None, fake, fake, 16384, None) == -1    # view 1 needs maps
+    assert lib.psfs_foreground_model(h, imgs, None, fake, fake, fake, 16383, None) == -4
+    assert lib.psfs_set_foreground(h, C.c_void_p(0x100002)) == -1
+    assert lib.psfs_set_foreground(h, fake) == 0
+    assert lib.psfs_set_foreground(h, None) == 0
+    lib.psfs_plan_destroy(h)
+
+
 def test_empty_work_is_a_no_op_without_device(lib):
     h = _plan(lib)
     assert lib.psfs_set_cameras(h, 0, None) == 0
