@@ -352,3 +352,76 @@ def fd_subgrid(grid: Grid, body: Sequence[Ellipsoid], size: int = 16):
     lo = [min(max(c[d] - size // 2, 0), max(dims[d] - size, 0)) for d in range(3)]
     hi = [min(lo[d] + size, dims[d]) for d in range(3)]
     return [lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]]
+
+
+# ------------------------------------------------------ tracking: particles/maps
+
+STREAM_PARTICLE = 7
+
+
+def body_cylinders(body: Sequence[Ellipsoid]) -> np.ndarray:
+    """FP64 [10][8] cylinders (A xyz, B xyz, rA, rB) of a body: each part's axis
+    is its ellipsoid's longest semi-axis, its radius the geometric mean of the
+    other two; limbs taper to 0.8 of that radius at their far end."""
+    out = np.zeros((len(body), 8))
+    for i, e in enumerate(body):
+        a = int(np.argmax(e.axes))
+        d = e.rot[:, a] * e.axes[a]
+        others = [e.axes[b] for b in range(3) if b != a]
+        r = float(np.sqrt(others[0] * others[1]))
+        out[i, 0:3] = e.centre - d
+        out[i, 3:6] = e.centre + d
+        out[i, 6] = r
+        out[i, 7] = r if i < 2 else 0.8 * r
+    return out
+
+
+def make_particles(rng: np.random.Generator, base: np.ndarray, n: int,
+                   sd_shift: float = 0.03, sd_end: float = 0.02, rad_jitter: float = 0.1) -> np.ndarray:
+    """FP32 [n][10][8]: the base cylinders moved as a whole by N(0, sd_shift) per
+    axis, each end point by N(0, sd_end), radii scaled by U(1 -+ rad_jitter)."""
+    base = np.asarray(base, np.float64)
+    p = np.repeat(base[None], n, axis=0)
+    shift = rng.normal(0.0, sd_shift, (n, 1, 3))
+    p[..., 0:3] += shift + rng.normal(0.0, sd_end, (n, base.shape[0], 3))
+    p[..., 3:6] += shift + rng.normal(0.0, sd_end, (n, base.shape[0], 3))
+    p[..., 6:8] *= rng.uniform(1.0 - rad_jitter, 1.0 + rad_jitter, (n, base.shape[0], 2))
+    return p.astype(np.float32)
+
+
+def _dilate(b: np.ndarray) -> np.ndarray:
+    """8-neighbour binary dilation with the border treated as 0."""
+    pad = np.pad(b, 1)
+    H, W = b.shape
+    out = np.zeros_like(b)
+    for dy in (0, 1, 2):
+        for dx in (0, 1, 2):
+            out |= pad[dy:dy + H, dx:dx + W]
+    return out
+
+
+def track_maps(mask: np.ndarray):
+    """Silhouette and edge maps (FP32 [H][W] in [0,1]) of one view's mask:
+    silhouette = the mask; edge = 1 on mask pixels with a 4-neighbour outside
+    the mask or the image, 2/3 within one pixel of those (8-neighbourhood), 1/3
+    within two, 0 elsewhere."""
+    m = np.asarray(mask, bool)
+    pad = np.pad(m, 1)
+    H, W = m.shape
+    inner = pad[0:H, 1:W + 1] & pad[2:H + 2, 1:W + 1] & pad[1:H + 1, 0:W] & pad[1:H + 1, 2:W + 2]
+    b0 = m & ~inner
+    b1 = _dilate(b0)
+    b2 = _dilate(b1)
+    edge = np.where(b0, 1.0, np.where(b1, 2.0 / 3.0, np.where(b2, 1.0 / 3.0, 0.0)))
+    return m.astype(np.float32), edge.astype(np.float32)
+
+
+def tracking_inputs(config: int = 1, frame: int = 0, n_particles: int = 200):
+    """Cameras, FP32 particle cylinders [n][10][8], silhouette and edge maps of
+    a workload's frame: the particles scatter around the cylinders of the
+    frame's body, the maps come from its ground-truth masks."""
+    fr = config_frame(config, frame)
+    base = body_cylinders(fr.body)
+    parts = make_particles(rng_for(config, frame, STREAM_PARTICLE), base, n_particles)
+    S, E = zip(*(track_maps(m) for m in fr.masks))
+    return fr.cams, parts, list(S), list(E)
