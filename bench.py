@@ -244,6 +244,7 @@ def main():
 
     surface = measure_surface(torch, psfs, slots[0], timed_graph, args)
     colour = measure_colour(torch, psfs, slots[0], frames[0], timed_graph, args)
+    particles = measure_particles(torch, psfs, S, timed_graph, args)
     diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
 
@@ -294,6 +295,7 @@ def main():
         "parity_max_abs_err": max_err,
         "surface": surface,
         "colour": colour,
+        "particles": particles,
         "fwd_bwd": diff,
         "batch": batch,
         "cpu_baseline": cpu,
@@ -364,6 +366,43 @@ def measure_colour(torch, psfs, slot, frame, timed_graph, args):
         out["cpu_oracle"] = {"us": 1e6 * (time.time() - t0), "cores": 1, "kind": "oracle",
                              "sample": "one run of the numpy FP64 oracle on the same list"}
     return out
+
+
+def measure_particles(torch, psfs, S, timed_graph, args, n_particles=200):
+    """Particle weights of one annealing layer: 200 particles of the 10-cylinder
+    model against the silhouette and edge maps of the 8 views of the 640x480
+    workload (weights kernel + normalisation), replayed from a HIP graph."""
+    cams, parts, Sm, Em = S.tracking_inputs(1, 0, n_particles)
+    plan = psfs.Plan(cams)
+    cyl = torch.from_numpy(parts).cuda()
+    sil = [torch.from_numpy(m).cuda() for m in Sm]
+    edg = [torch.from_numpy(m).cuda() for m in Em]
+    out = {"log_w": torch.empty(n_particles, dtype=torch.float64, device="cuda"),
+           "weights": torch.empty(n_particles, dtype=torch.float64, device="cuda")}
+
+    def f():
+        plan.particle_weights(cyl, sil, edg, beta=1.0, weights=True, out=out)
+
+    ms = timed_graph([f], max(50, args.steps // 2), 10)
+    samples = n_particles * len(cams) * 400          # 160 outline + 240 silhouette points per view
+    # algorithmic bytes: the cylinders, one FP32 map value per sample point, the outputs
+    algo = parts.nbytes + 4 * samples + 16 * n_particles
+    print(f"[bench] particle weights {ms * 1e3:.2f} us per layer ({n_particles} particles x {len(cams)} views)",
+          file=sys.stderr, flush=True)
+    res = {"workload": f"particle weights of one annealing layer: {n_particles} particles x 10 cylinders x "
+                       f"{len(cams)} views of 640x480 silhouette + edge maps",
+           "us": ms * 1e3, "layers_per_s": 1e3 / ms, "sample_points_per_s": samples / (ms * 1e-3),
+           "algorithmic_bytes": algo, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_cpu:
+        from oracle import particles as PT
+        t0 = time.time()
+        reps = 0
+        while reps < 1 or (time.time() - t0 < 2.0 and reps < 50):
+            PT.normalised(PT.log_weights(cams, parts, Sm, Em))
+            reps += 1
+        res["cpu_oracle"] = {"us": 1e6 * (time.time() - t0) / reps, "cores": 1, "kind": "oracle",
+                             "sample": f"{reps} runs of the numpy FP64 oracle on the same layer"}
+    return res
 
 
 def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):

@@ -255,6 +255,42 @@ int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t
                 float *colour_dev, int32_t *views_dev, void *workspace_dev, size_t workspace_bytes,
                 void *stream);
 
+/* ------------------------------------------ particle weights (tracking) */
+
+#define PSFS_CYLINDERS 10       /* cylinders of the body model (Table 1) */
+
+/* Weights of one layer's particle set in the annealed particle filter
+ * (Sec. 2.3.1 step 3, Eq. 10; Sec. 2.3.2, Eq. 14-16). A particle is its body
+ * model: PSFS_CYLINDERS cylinders (A xyz, B xyz, rA, rB), end points A != B,
+ * radii >= 0 (not checked). The paper does not say which points of the model
+ * are sampled; the reading taken: per cylinder and view (camera centre C, from
+ * P), 8 cross-sections at t = (m + 1/2) / 8 with centre X = A + t (B - A),
+ * radius r = rA + t (rB - rA); u = the unit component of X - C across the
+ * axis (length rho), e = unit axis x u;
+ *   outline points (Eq. 14)     X - (r^2/rho) u +- r sqrt(1 - r^2/rho^2) e
+ *                               (where the viewing ray touches the circle)
+ *   silhouette points (Eq. 15)  X, X +- (r/2) e.
+ * Each point reads the edge or silhouette map at its nearest pixel (the rule
+ * of psfs_fuse, computed in FP64); p = 0 behind the camera, outside the image,
+ * and for the five points of a cross-section with rho <= r. Per view
+ * Sigma_e = mean of 1 - p over the 160 outline points, Sigma_r over the 240
+ * silhouette points; log w = -(sum over views of Sigma_e + Sigma_r), views
+ * added in order; normalised weights = w^beta / sum over particles of w^beta
+ * (beta: the layer's annealing exponent; 1 = Eq. 16 as printed).
+ *   cylinders_dev   FP32 [np][PSFS_CYLINDERS][8], 16-byte aligned
+ *   silhouette_dev, edge_dev
+ *                   host arrays of n device pointers, FP32 [H][W] maps of view
+ *                   k (finite; 4-byte aligned)
+ *   beta            finite, >= 0; used only for weights_dev
+ *   log_w_dev       FP64 [np] output, required
+ *   weights_dev     nullable FP64 [np]: normalised weights
+ *   terms_dev       nullable FP64 [np][n][2]: (Sigma_e, Sigma_r) per view
+ * Needs cameras (n = 0 gives log w = 0). np in [0, 2^31); np = 0 is a no-op.
+ * Results are reproducible bit for bit. No workspace. */
+int psfs_particle_weights(psfs_plan *plan, const float *cylinders_dev, int64_t np,
+                          const float *const *silhouette_dev, const float *const *edge_dev, double beta,
+                          double *log_w_dev, double *weights_dev, double *terms_dev, void *stream);
+
 /* ---------------------------------------- differentiable variant (bilinear) */
 
 /* Workspace of psfs_diff_forward / psfs_diff_backward: likelihood maps,

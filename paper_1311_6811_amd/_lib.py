@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(PKG, "libpsfs.so")
 
 MAX_VIEWS = 16
 FG_BINS = 4096
+CYLINDERS = 10
 NEAREST, BILINEAR = 0, 1
 
 STATUS = {
@@ -76,6 +77,7 @@ SIGNATURES = {
     "psfs_foreground_model": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
     "psfs_set_foreground": (C.c_int, [vp, vp]),
     "psfs_colour": (C.c_int, [vp, C.POINTER(vp), vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]),
+    "psfs_particle_weights": (C.c_int, [vp, vp, C.c_int64, C.POINTER(vp), C.POINTER(vp), C.c_double, vp, vp, vp, vp]),
     "psfs_surface": (C.c_int, [vp, vp, vp, vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]),
     "psfs_threshold": (C.c_int, [vp, C.c_int64, C.c_float, vp, vp]),
     "psfs_diff_workspace_bytes": (C.c_size_t, [vp]),

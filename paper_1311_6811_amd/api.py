@@ -233,6 +233,40 @@ class Plan:
                                      ws.numel(), _stream()))
         return Surface(occ, smoothed, out, count, cap)
 
+    # ------------------------------------------------ particle weights
+    def particle_weights(self, cylinders: torch.Tensor, silhouettes: Sequence[torch.Tensor],
+                         edges: Sequence[torch.Tensor], beta: float = 1.0, weights: bool = True,
+                         terms: bool = False, out=None):
+        """log w of every particle (FP64 [np]) from its body-model cylinders
+        (FP32 [np][10][8]: A xyz, B xyz, rA, rB) and each view's silhouette and
+        edge maps (FP32 [H][W]); with `weights`, also w^beta normalised over the
+        particles; with `terms`, the per-view (Sigma_e, Sigma_r) [np][n][2].
+        Returns (log_w, weights or None, terms or None)."""
+        nc = L.CYLINDERS
+        if cylinders.dim() != 3 or tuple(cylinders.shape[1:]) != (nc, 8):
+            raise ValueError(f"cylinders must have shape (np, {nc}, 8), got {tuple(cylinders.shape)}")
+        npart = int(cylinders.shape[0])
+        if len(silhouettes) != self.n or len(edges) != self.n:
+            raise ValueError(f"expected {self.n} silhouette and edge maps")
+        sil = L.ptr_array([_dev(m, torch.float32, f"silhouettes[{k}]", (c.height, c.width))
+                           for k, (m, c) in enumerate(zip(silhouettes, self.cams))])
+        edg = L.ptr_array([_dev(m, torch.float32, f"edges[{k}]", (c.height, c.width))
+                           for k, (m, c) in enumerate(zip(edges, self.cams))])
+        o = out or {}
+        log_w = o.get("log_w")
+        log_w = log_w if log_w is not None else torch.empty(npart, dtype=torch.float64, device="cuda")
+        w = o.get("weights")
+        w = w if w is not None or not weights else torch.empty(npart, dtype=torch.float64, device="cuda")
+        t = o.get("terms")
+        t = t if t is not None or not terms else torch.empty((npart, self.n, 2), dtype=torch.float64, device="cuda")
+        L.check(L.lib().psfs_particle_weights(
+            self._h, _dev(cylinders, torch.float32, "cylinders") if npart else None, npart, sil, edg, float(beta),
+            _dev(log_w, torch.float64, "log_w", (npart,)) if npart else None,
+            _dev(w, torch.float64, "weights", (npart,)) if (w is not None and npart) else None,
+            _dev(t, torch.float64, "terms", (npart, self.n, 2)) if (t is not None and npart) else None,
+            _stream()))
+        return log_w, w, t
+
     # ------------------------------------- foreground model after frame 1
     def foreground_model(self, images: Sequence[torch.Tensor], masks=None, lmap: Optional[torch.Tensor] = None,
                          out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "host_util.h"
+#include "particles.h"
 
 struct psfs_plan {
     int n = -1;                                     // -1: cameras not set
@@ -662,6 +663,50 @@ int psfs_set_foreground(psfs_plan *plan, const float *log_density_dev)
     if (log_density_dev && !aligned(log_density_dev, 4)) return fail(PSFS_E_ARG, "log_density must be 4-byte aligned");
     plan->fg = log_density_dev;
     return PSFS_OK;
+}
+
+int psfs_particle_weights(psfs_plan *plan, const float *cylinders_dev, int64_t np,
+                          const float *const *silhouette_dev, const float *const *edge_dev, double beta,
+                          double *log_w_dev, double *weights_dev, double *terms_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_cameras(plan);
+    if (rc) return rc;
+    if (np < 0 || np >= (int64_t(1) << 31)) return fail(PSFS_E_RANGE, "particle count %lld out of range", static_cast<long long>(np));
+    if (weights_dev && !(std::isfinite(beta) && beta >= 0.0)) return fail(PSFS_E_RANGE, "beta must be finite and >= 0");
+    if (np == 0) return PSFS_OK;
+    if (!cylinders_dev || !aligned(cylinders_dev, 16)) return fail(PSFS_E_ARG, "cylinders must be a 16-byte aligned device pointer");
+    if (!log_w_dev || !aligned(log_w_dev, 8)) return fail(PSFS_E_ARG, "log_w must be an 8-byte aligned device pointer");
+    if (weights_dev && !aligned(weights_dev, 8)) return fail(PSFS_E_ARG, "weights must be 8-byte aligned");
+    if (terms_dev && !aligned(terms_dev, 8)) return fail(PSFS_E_ARG, "terms must be 8-byte aligned");
+    if (plan->n > 0 && (!silhouette_dev || !edge_dev)) return fail(PSFS_E_ARG, "map arrays are NULL");
+    for (int k = 0; k < plan->n; ++k) {
+        if (!silhouette_dev[k] || !aligned(silhouette_dev[k], 4)) return fail(PSFS_E_ARG, "silhouette map of view %d must be a 4-byte aligned device pointer", k);
+        if (!edge_dev[k] || !aligned(edge_dev[k], 4)) return fail(PSFS_E_ARG, "edge map of view %d must be a 4-byte aligned device pointer", k);
+    }
+    if ((rc = check_device())) return rc;
+    PartArgs a{};
+    for (int k = 0; k < plan->n; ++k) {
+        a.view[k].sil = silhouette_dev[k];
+        a.view[k].edge = edge_dev[k];
+        a.view[k].w = plan->cams[k].width;
+        a.view[k].h = plan->cams[k].height;
+        std::memcpy(a.view[k].P, plan->cams[k].P, sizeof(a.view[k].P));
+    }
+    a.cyl = cylinders_dev;
+    a.logw = log_w_dev;
+    a.terms = terms_dev;
+    a.np = np;
+    a.n = plan->n;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_particle_weights(a, s);
+    if (e != hipSuccess) return hip_fail(e, "particle weight kernel launch");
+    if (weights_dev) {
+        e = launch_particle_normalise(NormArgs{log_w_dev, weights_dev, np, beta}, s);
+        if (e != hipSuccess) return hip_fail(e, "particle normalisation kernel launch");
+    }
+    return PSFS_OK;
+    PSFS_GUARD_END
 }
 
 size_t psfs_diff_workspace_bytes(const psfs_plan *plan)

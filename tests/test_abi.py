@@ -231,6 +231,29 @@ def test_foreground_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_particle_weights_validation_without_device(lib):
+    h = _plan(lib)
+    fake = C.c_void_p(0x100000)
+    maps = L.ptr_array([0x100000, 0x100000])
+    out = C.c_void_p(0x200000)
+    assert lib.psfs_particle_weights(h, fake, 4, maps, maps, 1.0, out, out, out, None) == -3     # cameras missing
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    assert lib.psfs_particle_weights(h, fake, -1, maps, maps, 1.0, out, out, out, None) == -2
+    assert lib.psfs_particle_weights(h, fake, 1 << 31, maps, maps, 1.0, out, out, out, None) == -2
+    assert lib.psfs_particle_weights(h, fake, 4, maps, maps, -0.5, out, out, out, None) == -2    # beta < 0
+    assert lib.psfs_particle_weights(h, fake, 4, maps, maps, float("nan"), out, out, out, None) == -2
+    assert lib.psfs_particle_weights(h, None, 4, maps, maps, 1.0, out, out, out, None) == -1
+    assert lib.psfs_particle_weights(h, C.c_void_p(0x100008), 4, maps, maps, 1.0, out, out, out, None) == -1  # not 16-aligned
+    assert lib.psfs_particle_weights(h, fake, 4, maps, maps, 1.0, None, out, out, None) == -1      # log_w required
+    assert lib.psfs_particle_weights(h, fake, 4, maps, maps, 1.0, C.c_void_p(0x200004), None, None, None) == -1
+    assert lib.psfs_particle_weights(h, fake, 4, None, maps, 1.0, out, None, None, None) == -1
+    holes = L.ptr_array([0x100000, 0])
+    assert lib.psfs_particle_weights(h, fake, 4, maps, holes, 1.0, out, None, None, None) == -1   # view 1 edge map
+    assert lib.psfs_particle_weights(h, fake, 0, None, None, 1.0, None, None, None, None) == 0    # no particles: no-op
+    lib.psfs_plan_destroy(h)
+
+
 def test_empty_work_is_a_no_op_without_device(lib):
     h = _plan(lib)
     assert lib.psfs_set_cameras(h, 0, None) == 0
