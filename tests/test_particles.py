@@ -98,6 +98,21 @@ def test_parity_random_maps_and_beta():
     check(cams, parts, Sm, Em, beta=0.3)
 
 
+@pytest.mark.parametrize("nviews", [1, 3, 5, 12, 16])
+def test_view_counts(nviews):
+    """Each view count splits the 80 (cylinder, cross-section) pairs over its
+    own number of waves per view (16 // n): one to sixteen."""
+    say(f"particle weights, {nviews} views")
+    if nviews == 12:
+        cams, parts, Sm, Em = S.tracking_inputs(2, 0, 48)
+    else:
+        cams, parts, Sm, Em = S.tracking_inputs(1, 3, 48)
+        idx = [k % len(cams) for k in range(nviews)] if nviews > len(cams) else list(range(0, 8, 8 // nviews))[:nviews]
+        cams, Sm, Em = [cams[k] for k in idx], [Sm[k] for k in idx], [Em[k] for k in idx]
+    assert len(cams) == nviews
+    check(cams, parts, Sm, Em, beta=1.5)
+
+
 def test_hand_case():
     import json
     import os
