@@ -166,3 +166,35 @@ def test_degenerate_cases():
     lw, w, t = plan.particle_weights(torch.empty((0, 10, 8), dtype=torch.float32, device="cuda"), to_dev(Sm), to_dev(Em))
     torch.cuda.synchronize()
     assert lw.numel() == 0 and w.numel() == 0
+
+
+def test_graph_replays_match_eager():
+    """Captured once into a HIP graph and replayed three times, with eager
+    launches and synchronisations between the replays: every replay gives the
+    eager bits."""
+    say("particle weights, graph replays")
+    cams, parts, Sm, Em = S.tracking_inputs(0, 4, 128)
+    plan = psfs.Plan(cams)
+    cyl = torch.from_numpy(parts).cuda()
+    sil, edg = to_dev(Sm), to_dev(Em)
+    out = {"log_w": torch.empty(128, dtype=torch.float64, device="cuda"),
+           "weights": torch.empty(128, dtype=torch.float64, device="cuda")}
+    lw0, w0, _ = plan.particle_weights(cyl, sil, edg, beta=0.7)
+    torch.cuda.synchronize()
+    lw0, w0 = lw0.clone(), w0.clone()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.particle_weights(cyl, sil, edg, beta=0.7, out=out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            plan.particle_weights(cyl, sil, edg, beta=0.7, out=out)
+    for r in range(3):
+        out["log_w"].fill_(float("nan"))
+        out["weights"].fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out["log_w"], lw0), r
+        assert torch.equal(out["weights"], w0), r
+        plan.particle_weights(cyl, sil, edg, beta=0.7)      # eager work between replays
+        torch.cuda.synchronize()
