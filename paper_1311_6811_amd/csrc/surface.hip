@@ -91,12 +91,16 @@ __global__ __launch_bounds__(256) void surface_flag_kernel(SurfArgs a)
     for (int r = 0; r < kPerLane; ++r) {
         const int64_t v = v0 + 256 * r;
         if (v < a.nvox) {
-            bool surf = false;
-            if (a.occ[v]) {
-                surf = i == 0 || i + 1 == a.nx || j == 0 || j + 1 == a.ny || k == 0 || k + 1 == a.nz ||
-                       !a.occ[v - 1] || !a.occ[v + 1] || !a.occ[v - a.nx] || !a.occ[v + a.nx] ||
-                       !a.occ[v - plane] || !a.occ[v + plane];
-            }
+            // all seven loads at in-grid addresses (a face on the grid's border
+            // reads the voxel itself, the border test decides there), issued
+            // together rather than one after another
+            const bool border = (i == 0) | (i + 1 == a.nx) | (j == 0) | (j + 1 == a.ny) | (k == 0) | (k + 1 == a.nz);
+            const uint8_t o = a.occ[v];
+            const uint8_t xm = a.occ[i > 0 ? v - 1 : v], xp = a.occ[i + 1 < a.nx ? v + 1 : v];
+            const uint8_t ym = a.occ[j > 0 ? v - a.nx : v], yp = a.occ[j + 1 < a.ny ? v + a.nx : v];
+            const uint8_t zm = a.occ[k > 0 ? v - plane : v], zp = a.occ[k + 1 < a.nz ? v + plane : v];
+            const bool hole = (xm == 0) | (xp == 0) | (ym == 0) | (yp == 0) | (zm == 0) | (zp == 0);
+            const bool surf = (o != 0) & (border | hole);
             a.flags[v] = surf ? 1 : 0;
             c += surf;
         }
