@@ -338,8 +338,9 @@ typedef struct psfs_batch psfs_batch;  /* opaque */
 
 /* Plans a batch of nframes (1..65536) frames of uneven shapes processed by two
  * persistent launches (likelihood maps of every view of every frame, then
- * fusion of every frame, frames in decreasing voxels x views order) whose
- * workgroups pull work items from device counters. The launches are captured
+ * fusion of every frame, frames in decreasing voxels x views order, whose
+ * workgroups pull voxel bricks from device counters, one contiguous slice of
+ * bricks per XCD first). The launches are captured
  * into a HIP graph on the first run and replayed afterwards. Every frame's
  * result is bit-identical to psfs_reconstruct of that frame alone (same
  * params). Uses params.sampling (nearest, or the bilinear posterior).
@@ -353,7 +354,7 @@ size_t psfs_batch_workspace_bytes(const psfs_batch *batch);
  * the workspace pointer or the tile changes). On the null stream, or on a
  * stream the caller is capturing, the kernels are launched directly. Runs of
  * one batch must be ordered (one stream, or synchronised by the caller); they
- * share the workspace, which holds the likelihood maps and two counters. Must
+ * share the workspace, which holds the likelihood maps and the work counters. Must
  * run on the device the batch was created on (PSFS_E_DEVICE otherwise). */
 int psfs_batch_run(psfs_batch *batch, void *workspace_dev, size_t workspace_bytes, void *stream);
 /* Replaces the frames' pointers, camera matrices and grid placement (origin,

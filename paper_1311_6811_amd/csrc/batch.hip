@@ -1,15 +1,19 @@
 // Batched occupancy pass over many frames of uneven shape (grid size, view
-// count, image size), as two persistent launches that pull work items from
-// device counters:
+// count, image size), as two persistent launches:
 //   batch_slm_kernel   items = 1024-pixel chunks of every view of every frame
 //                      (Eq. 1-2 into one likelihood-map arena)
-//   batch_fuse_kernel  items = voxel bricks of every frame (Eq. 3-9 + threshold),
-//                      frames in decreasing cost order (longest first)
-// A workgroup pops kGroup consecutive items per atomic, finds the owning
-// view/frame by binary search in the device descriptor table, and runs the
-// same per-pixel and per-column code as the single-frame kernels, so a batched
-// frame is bit-identical to the same frame reconstructed alone. Every
-// workgroup leaves its loop when the counter passes the item count.
+//   batch_fuse_kernel  items = voxel bricks of every frame (Eq. 3-9 +
+//                      threshold), frames in decreasing cost order (longest
+//                      first)
+// Workgroups pop kGroup consecutive items per atomic from device counters.
+// The bricks are cut into one contiguous slice per XCD; the workgroups of an
+// XCD pop their own slice first (a band of z-slabs of the same frames, so the
+// XCD's L2 holds the matching band of map rows), then help with the other
+// slices. A workgroup finds the owning view/frame of an item by binary search
+// in the device descriptor table, and runs
+// the same per-pixel and per-column code as the single-frame kernels, so a
+// batched frame is bit-identical to the same frame reconstructed alone. Every
+// workgroup leaves when the counters it pops from have passed their ends.
 #include "kernels_common.h"
 
 namespace psfs {
@@ -19,6 +23,8 @@ using namespace dev;
 
 constexpr int kChunkPixels = 4 * kWavePixels;   // one per wave of a workgroup
 constexpr int kGroup = 4;               // items popped per atomic
+constexpr int kChunkCounter = 0;        // counters[0]: likelihood chunks popped
+constexpr int kCounters = 1 + kNumXcd;  // counters[1 + x]: bricks popped from slice x
 
 __device__ __forceinline__ int find_view(const BatchView *views, int nviews, int64_t chunk)
 {
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(256) void batch_slm_kernel(BatchArgs a)
     __shared__ SlmStage stage[4];
     const int wave = static_cast<int>(threadIdx.x >> 6);
     for (;;) {
-        const int64_t c0 = pop(a.counters + 0);
+        const int64_t c0 = pop(a.counters + kChunkCounter);
         if (c0 >= a.nchunks) break;
         const int64_t c1 = c0 + kGroup < a.nchunks ? c0 + kGroup : a.nchunks;
         for (int64_t c = c0; c < c1; ++c) {
@@ -75,31 +81,37 @@ __global__ __launch_bounds__(256) void batch_slm_kernel(BatchArgs a)
 template <int TX, int TY, int KZ, int SAMPLING>
 __global__ __launch_bounds__(TX * TY) void batch_fuse_kernel(BatchArgs a)
 {
-    for (;;) {
-        const int64_t b0 = pop(a.counters + 1);
-        if (b0 >= a.nbricks) break;
-        const int64_t b1 = b0 + kGroup < a.nbricks ? b0 + kGroup : a.nbricks;
-        for (int64_t b = b0; b < b1; ++b) {
-            const int f = __builtin_amdgcn_readfirstlane(find_frame(a.frames, a.nframes, b));
-            const BatchFrame &fr = a.frames[f];
-            const int64_t lb = b - fr.brick0;
-            const int ntx = (fr.grid.nx + TX - 1) / TX, nty = (fr.grid.ny + TY - 1) / TY;
-            const int64_t ntile = static_cast<int64_t>(ntx) * nty;
-            const int64_t zc = lb / ntile;
-            const int t = static_cast<int>(lb - zc * ntile);
-            const int tyi = t / ntx, txi = t - tyi * ntx;
-            const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
-            const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
-            const BatchView *views = a.views + fr.view0;
-            fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return views[v].g; }, fr.n, a.lmap, fr.grid,
-                                      i, j, static_cast<int>(zc) * KZ, a.L0, a.tau, fr.post, fr.occ);
+    // workgroups are dispatched to the XCDs in turn
+    const int home = static_cast<int>(blockIdx.x % kNumXcd);
+    for (int q = 0; q < kNumXcd; ++q) {
+        const int slice = (home + q) % kNumXcd;
+        const int64_t lo = a.nbricks * slice / kNumXcd, hi = a.nbricks * (slice + 1) / kNumXcd;
+        for (;;) {
+            const int64_t b0 = lo + pop(a.counters + 1 + slice);
+            if (b0 >= hi) break;
+            const int64_t b1 = b0 + kGroup < hi ? b0 + kGroup : hi;
+            for (int64_t b = b0; b < b1; ++b) {
+                const int f = __builtin_amdgcn_readfirstlane(find_frame(a.frames, a.nframes, b));
+                const BatchFrame &fr = a.frames[f];
+                const int64_t lb = b - fr.brick0;
+                const int ntx = (fr.grid.nx + TX - 1) / TX, nty = (fr.grid.ny + TY - 1) / TY;
+                const int64_t ntile = static_cast<int64_t>(ntx) * nty;
+                const int64_t zc = lb / ntile;
+                const int t = static_cast<int>(lb - zc * ntile);
+                const int tyi = t / ntx, txi = t - tyi * ntx;
+                const int i = txi * TX + static_cast<int>(threadIdx.x % TX);
+                const int j = tyi * TY + static_cast<int>(threadIdx.x / TX);
+                const BatchView *views = a.views + fr.view0;
+                fuse_column<TX, KZ, SAMPLING>([&](int v) -> const ViewGeom & { return views[v].g; }, fr.n, a.lmap,
+                                              fr.grid, i, j, static_cast<int>(zc) * KZ, a.L0, a.tau, fr.post, fr.occ);
+            }
         }
     }
 }
 
 __global__ void batch_reset_kernel(unsigned long long *counters)
 {
-    if (threadIdx.x < 2) counters[threadIdx.x] = 0ull;
+    if (threadIdx.x < kCounters) counters[threadIdx.x] = 0ull;
 }
 
 template <int S>

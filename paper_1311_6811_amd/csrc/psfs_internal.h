@@ -136,7 +136,7 @@ struct BatchArgs {
     const BatchView *views;
     const BatchFrame *frames;           // decreasing cost order
     float *lmap;
-    unsigned long long *counters;       // [0] chunks popped, [1] bricks popped
+    unsigned long long *counters;       // work counters (a 256-byte region), reset by the first launch
     int64_t nchunks, nbricks;
     int32_t nviews, nframes;
     float k0, L0, tau;
