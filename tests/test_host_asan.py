@@ -1,0 +1,46 @@
+"""The C ABI's host code (argument validation, plan and batch set-up, the
+batch descriptor table, error reporting) under AddressSanitizer, without a GPU.
+
+The two host-side sources are rebuilt with host-only ASan into a temporary
+library, linked with the kernel objects of the regular build, and driven by
+tests/asan_driver.c through every entry point's validation paths and the plan
+and batch lifecycles, with leak checking."""
+import glob
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1311_6811_amd", "csrc")
+BUILD = os.path.join(ROOT, "paper_1311_6811_amd", "_build")
+HIPCC = "/opt/rocm/bin/hipcc"
+CLANG = "/opt/rocm/llvm/bin/clang"
+HOST_ASAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+HOST_SOURCES = ("api.hip", "batch_api.hip")
+
+
+def test_host_code_under_asan(tmp_path):
+    objs = [o for o in sorted(glob.glob(os.path.join(BUILD, "*.o")))
+            if os.path.basename(o) not in tuple(s + ".o" for s in HOST_SOURCES)]
+    if not objs:
+        pytest.skip("kernel objects not built (paper_1311_6811_amd.build first)")
+    if not (os.path.exists(HIPCC) and os.path.exists(CLANG)):
+        pytest.skip("hipcc / clang not found")
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", os.path.join(ROOT, "include"),
+             "-I", CSRC, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + HOST_ASAN
+    asan_objs = []
+    for src in HOST_SOURCES:
+        o = str(tmp_path / (src + ".o"))
+        subprocess.run([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", o], check=True, capture_output=True)
+        asan_objs.append(o)
+    lib = str(tmp_path / "libpsfs_asan.so")
+    subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *HOST_ASAN[:2], "-o", lib, *asan_objs, *objs],
+                   check=True, capture_output=True)
+    exe = str(tmp_path / "asan_driver")
+    subprocess.run([CLANG, "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "asan_driver.c"), "-o", exe, "-L", str(tmp_path), "-lpsfs_asan",
+                    f"-Wl,-rpath,{tmp_path}", "-lm"], check=True, capture_output=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=23")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
