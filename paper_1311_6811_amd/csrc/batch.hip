@@ -10,10 +10,10 @@
 // XCD pop their own slice first (a band of z-slabs of the same frames, so the
 // XCD's L2 holds the matching band of map rows), then help with the other
 // slices. A workgroup finds the owning view/frame of an item by binary search
-// in the device descriptor table, and runs
-// the same per-pixel and per-column code as the single-frame kernels, so a
-// batched frame is bit-identical to the same frame reconstructed alone. Every
-// workgroup leaves when the counters it pops from have passed their ends.
+// in the device descriptor table and runs the same per-pixel and per-column
+// code as the single-frame kernels, so a batched frame is bit-identical to the
+// same frame reconstructed alone. Every workgroup leaves when the counters it
+// pops from have passed their ends.
 #include "kernels_common.h"
 
 namespace psfs {
@@ -24,7 +24,8 @@ using namespace dev;
 constexpr int kChunkPixels = 4 * kWavePixels;   // one per wave of a workgroup
 constexpr int kGroup = 4;               // items popped per atomic
 constexpr int kChunkCounter = 0;        // counters[0]: likelihood chunks popped
-constexpr int kCounters = 1 + kNumXcd;  // counters[1 + x]: bricks popped from slice x
+constexpr int kBrickCounter0 = 1;       // counters[1 + x]: bricks popped from slice x
+constexpr int kCounters = kBrickCounter0 + kNumXcd;
 
 __device__ __forceinline__ int find_view(const BatchView *views, int nviews, int64_t chunk)
 {
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(TX * TY) void batch_fuse_kernel(BatchArgs a)
         const int slice = (home + q) % kNumXcd;
         const int64_t lo = a.nbricks * slice / kNumXcd, hi = a.nbricks * (slice + 1) / kNumXcd;
         for (;;) {
-            const int64_t b0 = lo + pop(a.counters + 1 + slice);
+            const int64_t b0 = lo + pop(a.counters + kBrickCounter0 + slice);
             if (b0 >= hi) break;
             const int64_t b1 = b0 + kGroup < hi ? b0 + kGroup : hi;
             for (int64_t b = b0; b < b1; ++b) {
