@@ -41,7 +41,7 @@ def check(fr, plan, ims, idx_t):
     return int(keep.sum()), len(idx)
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
 def test_surface_voxel_colours(cfg):
     say(f"colour of the surface voxels, config {cfg}")
     fr = S.config_frame(cfg, 0)

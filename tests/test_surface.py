@@ -110,3 +110,42 @@ def test_solid_block_and_empty_grid():
     res = plan.surface(torch.empty((4, 4, 0), device="cuda"))
     torch.cuda.synchronize()
     assert int(res.count.item()) == 0
+
+
+def test_largest_workload_256cube_12_views():
+    """The 256^3 posterior of the 12-view 1280x720 workload, threshold 1/2. At
+    this size some smoothed values fall within the rounding band of the
+    threshold, so occupancy is compared where the oracle's smoothed value is
+    more than 1e-5 from it, and surface membership where the voxel and its six
+    face neighbours all are."""
+    say("surface of the 256^3 x 12-view posterior")
+    fr = S.config_frame(2, 0)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    post, _ = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    p = post.cpu().numpy()
+    tau = 0.5
+    sm, occ, idx = SO.extract(p.astype(np.float64), tau)
+    res = run(p, tau)
+    got_sm = res.smoothed.cpu().numpy().astype(np.float64)
+    assert np.abs(got_sm - sm).max() <= SMOOTH_TOL
+    clear = np.abs(sm - tau) > BAND
+    got_occ = res.occ.cpu().numpy()
+    assert np.array_equal(got_occ[clear], occ[clear])
+    decided = clear.copy()
+    pad = np.pad(clear, 1, constant_values=True)
+    for axis in range(3):
+        for d in (-1, 1):
+            decided &= np.roll(pad, d, axis=axis)[1:-1, 1:-1, 1:-1]
+    got = res.indices().cpu().numpy().astype(np.int64)
+    assert int(res.count.item()) == len(got)
+    assert np.all(np.diff(got) > 0)
+    flat = decided.ravel()
+    want_set = np.zeros(p.size, bool)
+    want_set[idx] = True
+    got_set = np.zeros(p.size, bool)
+    got_set[got] = True
+    assert np.array_equal(got_set[flat], want_set[flat])
+    say(f"  {len(got)} surface voxels, {int((~flat).sum())} undecided of {p.size}")
+    assert len(got) > 5000 and (~flat).mean() < 1e-3
