@@ -35,7 +35,7 @@ def two_frames(cfg):
     return f0, f1
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
 def test_learned_model_density_maps_and_posterior(cfg):
     say(f"foreground model, rig of config {cfg}")
     f0, f1 = two_frames(cfg)
