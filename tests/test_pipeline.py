@@ -61,6 +61,24 @@ def test_sequence_bitwise_equals_single_frames():
     assert_matches_single(plan, images, outs)
 
 
+def test_largest_workload_sequence():
+    """The 12-view 1280x720 rig over a 256^3 grid, 3 frames moving 2 cm per
+    frame: every pipelined frame bit-identical to the frame alone, the last
+    one within the posterior tolerance of the FP64 oracle."""
+    say("pipelined 256^3 x 12 views, 3 frames")
+    frames = [S.config_frame(2, f) for f in range(3)]
+    plan, images = sequence(frames)
+    outs = run_pipeline(plan, images)
+    assert_matches_single(plan, images, outs)
+    fr = frames[-1]
+    maps = [O.slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
+    ref = O.posterior(fr.cams, fr.grid, maps)
+    post, occ = outs[-1]
+    worst = assert_posterior_parity(post, ref, combos=lambda v: O.voxel_combos(fr.cams, fr.grid, maps, v))
+    assert_occupancy_parity(occ, ref)
+    say(f"  max posterior error {worst:.2e}")
+
+
 def test_ragged_sequence_and_oracle_parity():
     say("pipelined ragged grid, odd image sizes")
     rng = np.random.default_rng(21)
