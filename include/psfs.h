@@ -176,8 +176,8 @@ int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t 
 
 /* ------------------------------------------ foreground model after frame 1 */
 
-/* Eq. 1-2 take the foreground colour density as uniform (log_u) because the
- * foreground is unknown for the first frame (Sec. 2.2.2). For later frames a
+/* Eq. 1-2 take the foreground colour density as uniform (log_u), as nothing
+ * is known of the foreground's colours at the first frame (Sec. 2.2.2). For later frames a
  * learned model can replace it (the paper implies one, without describing
  * it; this is the reading taken): a histogram of PSFS_FG_BINS colour bins
  * (bin = (R >> 4) * 256 + (G >> 4) * 16 + (B >> 4)) of the foreground pixels

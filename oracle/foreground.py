@@ -4,8 +4,8 @@ first.
 TEST INFRASTRUCTURE ONLY: used by ``tests/``; the product library never
 imports this package.
 
-Eq. 1-2 take the foreground likelihood of a pixel colour as uniform because
-the foreground is unknown for the first frame (Sec. 2.2.2); the paper implies
+Eq. 1-2 take the foreground likelihood of a pixel colour as uniform, as
+nothing is known of the foreground's colours at the first frame (Sec. 2.2.2); the paper implies
 but does not describe the model used afterwards. The reading taken here:
 
 * the foreground likelihood is a colour histogram of 16 x 16 x 16 bins over

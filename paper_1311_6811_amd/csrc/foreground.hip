@@ -1,6 +1,6 @@
 // Learned foreground colour model for frames after the first (Eq. 1-2 use a
-// uniform foreground density because the foreground is unknown for the first
-// frame, Sec. 2.2.2). Three launches:
+// uniform foreground density, as nothing is known of the foreground's colours
+// at the first frame, Sec. 2.2.2). Three launches:
 //   fg_zero_kernel     bin counts to 0
 //   fg_hist_kernel     per workgroup an LDS histogram of the foreground pixels
 //                      (mask != 0, or log(2*SLM) > 0 of the previous frame)
