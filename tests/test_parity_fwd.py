@@ -77,6 +77,48 @@ def test_forward_parity_large_grid_12_views():
     assert_occupancy_parity(occ, ref)
 
 
+def test_largest_grid_index_range():
+    """A 1290^3 grid (2,146,689,000 voxels, just under the 2^31 limit the header
+    states) seen by 4 views: the first and last voxels, the ends of rows and
+    planes, and random voxels inside and around the body, each within 1e-5 of
+    one of the posteriors the per-voxel oracle admits; occupancy consistent."""
+    say("forward at 1290^3 voxels x 4 views (sampled)")
+    f, W, H = S.IMAGE_CLASSES[0]
+    cams = S.ring_rig(4, f, W, H)
+    grid = S.cube_grid(1290, 2.0)
+    V = grid.nvox
+    assert V < 2 ** 31
+    rng = np.random.default_rng(77)
+    body = S.make_body(rng)
+    fr = S.render_frame(13, 0, cams, grid, body, (13, 0))
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    post, occ = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    nx, ny = grid.nx, grid.ny
+    ends = [0, 1, nx - 1, nx, nx * ny - 1, nx * ny, V // 2, V - nx * ny, V - nx, V - 2, V - 1]
+    h, o = float(grid.voxel), float(grid.origin[0])
+    c = body[0].centre
+    near = [((int((c[2] - o) / h) + dk) * ny + int((c[1] - o) / h) + dj) * nx + int((c[0] - o) / h) + di
+            for di, dj, dk in rng.integers(-20, 21, (300, 3))]
+    idx = np.array(ends + near + list(rng.integers(0, V, 300)), np.int64)
+    t = torch.from_numpy(idx).cuda()
+    gp = post.view(-1)[t].cpu().numpy().astype(np.float64)
+    go = occ.view(-1)[t].cpu().numpy()
+    del post, occ
+    torch.cuda.empty_cache()
+    maps = [O.slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
+    occupied = 0
+    for v, p, oc in zip(idx, gp, go):
+        combos = O.voxel_combos(cams, grid, maps, int(v))
+        assert len(combos) > 0
+        assert np.min(np.abs(combos - p)) <= 1e-5, f"voxel {v}: {p} vs {combos[:4]}"
+        assert oc == (1 if p > 0.5 else 0)
+        occupied += int(oc)
+    assert occupied > 20
+    say(f"  {len(idx)} voxels checked, {occupied} occupied")
+
+
 def test_ragged_grid_odd_images_mixed_sizes():
     say("ragged grid 37x29x23, odd image sizes")
     rng = np.random.default_rng(5)
