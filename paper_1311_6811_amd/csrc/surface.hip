@@ -8,9 +8,13 @@
 //   surface_flag_kernel    surface flag of every voxel (occupied, with an
 //                          unoccupied or out-of-grid face neighbour) and, per
 //                          block of kSurfBlock consecutive voxels, their count
+//   surface_scan_kernel    (grids of more than kScanMin blocks) the block
+//                          offsets: exclusive prefix of the counts, one
+//                          workgroup
 //   surface_write          the flagged voxels' linear indices at their place
 //                          in the ascending list (block offset = sum of the
-//                          earlier blocks' counts)
+//                          earlier blocks' counts, summed by each block itself
+//                          on smaller grids)
 // The paper keeps inner-voxel removal on the CPU; here it is a deterministic
 // two-kernel stream compaction over a flag grid.
 #include "psfs_internal.h"
@@ -21,6 +25,8 @@ namespace {
 constexpr int kColZ = 8;                            // z-values per lane in smooth_kernel
 constexpr int kSurfBlock = 4096;                    // voxels per compaction block (16 per lane)
 constexpr int kPerLane = kSurfBlock / 256;
+constexpr int kScanThreads = 1024;
+constexpr int kScanMin = 4096;                      // more blocks: offsets from surface_scan_kernel
 
 // 3x3x3 mean over the in-grid neighbours and threshold. A lane owns kColZ
 // voxels of one (x, y) column: for each plane z it sums the 3 x 3 window of
@@ -158,12 +164,40 @@ __device__ __forceinline__ int block_inclusive_scan(int x, int *wave_tot)
     return x;
 }
 
-__global__ __launch_bounds__(256) void surface_write_kernel(SurfArgs a)
+// Exclusive prefix of the block counts, written over them as offsets, and the
+// total: one workgroup; thread t owns a contiguous range of blocks, so the
+// additions run in block order within a range and in thread order across the
+// ranges (offsets are below nvox < 2^31).
+__global__ __launch_bounds__(kScanThreads) void surface_scan_kernel(SurfArgs a)
 {
-    __shared__ int64_t red[256];
-    __shared__ int wave_tot[4];
-    const int b = static_cast<int>(blockIdx.x);
-    // exclusive prefix of the block counts (and, in block 0, the total)
+    __shared__ int64_t part[kScanThreads];
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t per = (static_cast<int64_t>(a.nblocks) + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = t * per < a.nblocks ? t * per : a.nblocks;
+    const int64_t hi = lo + per < a.nblocks ? lo + per : a.nblocks;
+    int64_t s = 0;
+    for (int64_t q = lo; q < hi; ++q) s += a.counts[q];
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const int64_t add = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int64_t run = part[t] - s;
+    for (int64_t q = lo; q < hi; ++q) {
+        const int32_t c = a.counts[q];
+        a.counts[q] = static_cast<int32_t>(run);
+        run += c;
+    }
+    if (t == kScanThreads - 1) *a.count = part[t];
+}
+
+// Block b's offset summed by the block itself over the earlier blocks' counts
+// (and, in block 0, the total into *count); every thread of the block calls it.
+__device__ __forceinline__ int64_t own_block_offset(const SurfArgs &a, int b, int64_t *red)
+{
     int64_t s = 0, tot = 0;
     for (int q = static_cast<int>(threadIdx.x); q < a.nblocks; q += 256) {
         if (q < b) s += a.counts[q];
@@ -175,7 +209,7 @@ __global__ __launch_bounds__(256) void surface_write_kernel(SurfArgs a)
         if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    const int64_t block_off = red[0];
+    const int64_t off = red[0];
     __syncthreads();
     if (b == 0) {
         red[threadIdx.x] = tot;
@@ -186,6 +220,16 @@ __global__ __launch_bounds__(256) void surface_write_kernel(SurfArgs a)
         }
         if (threadIdx.x == 0) *a.count = red[0];
     }
+    return off;
+}
+
+// scanned: the counts already hold the block offsets (surface_scan_kernel)
+__global__ __launch_bounds__(256) void surface_write_kernel(SurfArgs a, int scanned)
+{
+    __shared__ int64_t red[256];
+    __shared__ int wave_tot[4];
+    const int b = static_cast<int>(blockIdx.x);
+    const int64_t block_off = scanned ? static_cast<int64_t>(a.counts[b]) : own_block_offset(a, b, red);
     const int64_t base = static_cast<int64_t>(b) * kSurfBlock;
     uint32_t bits = lane_flags(a, base);
     const int c = __popc(bits);
@@ -218,7 +262,9 @@ hipError_t launch_surface(const SurfArgs &a, hipStream_t s)
     const dim3 sg(static_cast<unsigned>((cols + 3) / 4), static_cast<unsigned>((a.nz + kColZ - 1) / kColZ));
     hipLaunchKernelGGL(smooth_kernel, sg, dim3(256), 0, s, a);
     hipLaunchKernelGGL(surface_flag_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(surface_write_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
+    const int scanned = a.nblocks > kScanMin ? 1 : 0;
+    if (scanned) hipLaunchKernelGGL(surface_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);
+    hipLaunchKernelGGL(surface_write_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a, scanned);
     return hipGetLastError();
 }
 

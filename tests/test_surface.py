@@ -112,20 +112,11 @@ def test_solid_block_and_empty_grid():
     assert int(res.count.item()) == 0
 
 
-def test_largest_workload_256cube_12_views():
-    """The 256^3 posterior of the 12-view 1280x720 workload, threshold 1/2. At
-    this size some smoothed values fall within the rounding band of the
-    threshold, so occupancy is compared where the oracle's smoothed value is
-    more than 1e-5 from it, and surface membership where the voxel and its six
-    face neighbours all are."""
-    say("surface of the 256^3 x 12-view posterior")
-    fr = S.config_frame(2, 0)
-    ims, mus, vs = upload(fr)
-    plan = plan_for(fr, mus, vs)
-    post, _ = plan.reconstruct(ims)
-    torch.cuda.synchronize()
-    p = post.cpu().numpy()
-    tau = 0.5
+def check_banded(p, tau=0.5):
+    """Smoothed values within tolerance everywhere; occupancy where the
+    oracle's smoothed value is clear of the threshold band; surface membership
+    where the voxel and its six face neighbours all are. Returns (surface
+    voxels, undecided voxels)."""
     sm, occ, idx = SO.extract(p.astype(np.float64), tau)
     res = run(p, tau)
     got_sm = res.smoothed.cpu().numpy().astype(np.float64)
@@ -147,5 +138,74 @@ def test_largest_workload_256cube_12_views():
     got_set = np.zeros(p.size, bool)
     got_set[got] = True
     assert np.array_equal(got_set[flat], want_set[flat])
-    say(f"  {len(got)} surface voxels, {int((~flat).sum())} undecided of {p.size}")
-    assert len(got) > 5000 and (~flat).mean() < 1e-3
+    return len(got), int((~flat).sum())
+
+
+def test_block_offsets_by_scan_kernel():
+    """More than 4096 compaction blocks (17.0 M voxels): the block offsets come
+    from the one-workgroup scan instead of each block's own sum."""
+    shape = (260, 256, 256)
+    say(f"surface on {shape} (scanned block offsets)")
+    n, und = check_banded(field(shape, 31, sigma=3.0))
+    say(f"  {n} surface voxels, {und} undecided")
+    assert n > 10000 and und < 5e-3 * np.prod(shape)
+
+
+def test_largest_workload_256cube_12_views():
+    """The 256^3 posterior of the 12-view 1280x720 workload, threshold 1/2. At
+    this size some smoothed values fall within the rounding band of the
+    threshold, so occupancy is compared where the oracle's smoothed value is
+    more than 1e-5 from it, and surface membership where the voxel and its six
+    face neighbours all are."""
+    say("surface of the 256^3 x 12-view posterior")
+    fr = S.config_frame(2, 0)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    post, _ = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    p = post.cpu().numpy()
+    n, und = check_banded(p)
+    say(f"  {n} surface voxels, {und} undecided of {p.size}")
+    assert n > 5000 and und < 1e-3 * p.size
+
+
+def test_largest_grid_properties():
+    """A 1290^3 grid (just under the 2^31-voxel limit, 524 k compaction blocks):
+    a smooth ball-shaped posterior made on the GPU; checked by properties that
+    hold at any size: the count equals the surface voxels of the returned
+    occupancy (occupied with an unoccupied or out-of-grid face neighbour), the
+    list is ascending and holds exactly those voxels, and sampled smoothed
+    values are the 3x3x3 in-grid means of the posterior."""
+    n = 1290
+    say(f"surface at {n}^3 (properties)")
+    ax = torch.arange(n, device="cuda", dtype=torch.float32) / (n - 1) * 2.0 - 1.0
+    r2 = ax.view(n, 1, 1) ** 2 + ax.view(1, n, 1) ** 2 + (1.3 * ax).view(1, 1, n) ** 2
+    post = torch.sigmoid(40.0 * (0.6 - r2)).contiguous()
+    del r2
+    grid = S.Grid(n, n, n, np.zeros(3, np.float32), np.float32(0.01))
+    plan = psfs.Plan(None, grid, threshold=0.5)
+    res = plan.surface(post, want_smoothed=True)
+    got = res.indices().to(torch.int64)
+    occ = res.occ.bool()
+    inner = torch.zeros_like(occ)
+    inner[1:-1, 1:-1, 1:-1] = (occ[:-2, 1:-1, 1:-1] & occ[2:, 1:-1, 1:-1] & occ[1:-1, :-2, 1:-1] &
+                               occ[1:-1, 2:, 1:-1] & occ[1:-1, 1:-1, :-2] & occ[1:-1, 1:-1, 2:])
+    surf = (occ & ~inner).view(-1)
+    del inner
+    count = int(res.count.item())
+    assert count == int(surf.sum().item()) == got.numel()
+    assert bool((got[1:] > got[:-1]).all().item())
+    assert bool(surf[got].all().item())
+    assert count > 100000
+    rng = np.random.default_rng(9)
+    ks, js, is_ = (rng.integers(0, n, 200) for _ in range(3))
+    ks[:4], js[:4], is_[:4] = [0, n - 1, 0, n - 1], [0, n - 1, n - 1, 0], [0, n - 1, 0, n - 1]
+    for k, j, i in zip(ks, js, is_):
+        lo = [max(c - 1, 0) for c in (k, j, i)]
+        hi = [min(c + 2, n) for c in (k, j, i)]
+        win = post[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]].double().cpu().numpy()
+        m = win.mean()
+        sm = float(res.smoothed[k, j, i].item())
+        assert abs(sm - m) <= SMOOTH_TOL, (k, j, i, sm, m)
+        assert int(res.occ[k, j, i].item()) == (1 if sm > 0.5 else 0)
+    say(f"  {count} surface voxels")
