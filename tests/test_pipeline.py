@@ -147,3 +147,17 @@ def test_zero_views_and_empty_grid():
     plan.set_backgrounds(mus, vs)
     outs = run_pipeline(plan, [ims, ims])
     assert all(p.numel() == 0 for p, _ in outs)
+
+
+def test_largest_grid_sequence_bitwise():
+    """Two frames over a 1290^3 grid (just under the 2^31-voxel limit) seen by
+    4 views: the pipelined frames are bit-identical to the frames alone."""
+    say("pipelined 1290^3 x 4 views, 2 frames")
+    f, W, H = S.IMAGE_CLASSES[0]
+    cams = S.ring_rig(4, f, W, H)
+    grid = S.cube_grid(1290, 2.0)
+    rng = np.random.default_rng(91)
+    frames = [S.render_frame(14, k, cams, grid, S.make_body(rng, shift=(0.03 * k, 0.0, 0.0)), (14, 0)) for k in range(2)]
+    plan, images = sequence(frames)
+    outs = run_pipeline(plan, images)
+    assert_matches_single(plan, images, outs)
