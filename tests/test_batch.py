@@ -157,3 +157,22 @@ def test_batch_with_empty_grid_and_no_occupancy_output():
     post, _ = single(fr0, bf0)
     torch.cuda.synchronize()
     assert torch.equal(post, bf0.posterior)
+
+
+def test_batch_with_the_largest_grid():
+    """A 1290^3 frame (just under the 2^31-voxel limit, ~2.1 M bricks) batched
+    with two small frames: every frame bit-identical to the frame alone."""
+    say("batch: 1290^3 x 4 views with two small frames")
+    f, W, H = S.IMAGE_CLASSES[0]
+    cams = S.ring_rig(4, f, W, H)
+    rng = np.random.default_rng(93)
+    frames = [S.render_frame(15, 0, cams, S.cube_grid(1290, 2.0), S.make_body(rng), (15, 0)),
+              S.config_frame(3, 0), S.config_frame(3, 1)]
+    bfs = [to_batch_frame(fr) for fr in frames]
+    b = psfs.Batch(bfs)
+    b.run()
+    torch.cuda.synchronize()
+    for fr, bf in zip(frames, bfs):
+        post, occ = single(fr, bf)
+        torch.cuda.synchronize()
+        assert torch.equal(post, bf.posterior) and torch.equal(occ, bf.occ)
