@@ -261,8 +261,8 @@ int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t
 
 /* Weights of one layer's particle set in the annealed particle filter
  * (Sec. 2.3.1 step 3, Eq. 10; Sec. 2.3.2, Eq. 14-16). A particle is its body
- * model: PSFS_CYLINDERS cylinders (A xyz, B xyz, rA, rB), end points A != B,
- * radii >= 0 (not checked). The paper does not say which points of the model
+ * model: PSFS_CYLINDERS cylinders (A xyz, B xyz, rA, rB), radii >= 0. The paper
+ * does not say which points of the model
  * are sampled; the reading taken: per cylinder and view (camera centre C, from
  * P), 8 cross-sections at t = (m + 1/2) / 8 with centre X = A + t (B - A),
  * radius r = rA + t (rB - rA); u = the unit component of X - C across the
@@ -272,7 +272,8 @@ int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t
  *   silhouette points (Eq. 15)  X, X +- (r/2) e.
  * Each point reads the edge or silhouette map at its nearest pixel (the rule
  * of psfs_fuse, computed in FP64); p = 0 behind the camera, outside the image,
- * and for the five points of a cross-section with rho <= r. Per view
+ * and for the five points of a cross-section with rho <= r or with geometry
+ * that is not finite (A = B, a non-finite coordinate or radius). Per view
  * Sigma_e = mean of 1 - p over the 160 outline points, Sigma_r over the 240
  * silhouette points; log w = -(sum over views of Sigma_e + Sigma_r), views
  * added in order; normalised weights = w^beta / sum over particles of w^beta

@@ -25,7 +25,8 @@ per particle, camera (centre C) and cylinder (end points A, B, radii rA, rB):
   (Eq. 3-9): pixel (floor(x / z + 1/2), floor(y / z + 1/2)) of (x, y, z) = P [X; 1];
   p is the map value there, and p = 0 when z <= 0, when the pixel lies outside
   the image, and for all five points of a cross-section whose circle contains
-  the camera centre (rho <= r), where no outline exists;
+  the camera centre (rho <= r), where no outline exists, or whose geometry is
+  not finite (A = B, or a non-finite coordinate or radius);
 * per camera: Sigma_e = mean over the 10 * 8 * 2 edge points of 1 - p,
   Sigma_r = mean over the 10 * 8 * 3 silhouette points of 1 - p;
   log w = -sum over cameras of (Sigma_e + Sigma_r);
@@ -50,6 +51,13 @@ def camera_centre(P) -> np.ndarray:
     return -np.linalg.solve(P[:, :3], P[:, 3])
 
 
+# Geometry that is not finite (A = B, NaN or infinite inputs) propagates NaN,
+# which the rho > r test and the image-bounds tests turn into p = 0; numpy's
+# warnings about it are silenced where it is computed.
+_quiet = np.errstate(invalid="ignore", divide="ignore", over="ignore")
+
+
+@_quiet
 def cross_sections(cyl: np.ndarray):
     """Centres X [..., 10, M, 3], radii r [..., 10, M] and unit axes a [..., 10, 1, 3]
     of the M cross-sections of each cylinder (A, B, rA, rB) in cyl [..., 10, 8]."""
@@ -64,6 +72,7 @@ def cross_sections(cyl: np.ndarray):
     return X, r, a[..., None, :]
 
 
+@_quiet
 def sample_points(cyl: np.ndarray, C: np.ndarray):
     """Edge points [..., 10, M, 2, 3], silhouette points [..., 10, M, 3, 3] and the
     mask [..., 10, M] of cross-sections that have outlines (rho > r), seen from C."""
@@ -71,7 +80,7 @@ def sample_points(cyl: np.ndarray, C: np.ndarray):
     w = X - np.asarray(C, np.float64)
     w = w - np.sum(w * a, axis=-1, keepdims=True) * a
     rho = np.linalg.norm(w, axis=-1)
-    valid = rho > r
+    valid = rho > r                                         # False for NaN geometry
     safe = np.where(valid, rho, 1.0)
     u = w / safe[..., None]
     e = np.cross(np.broadcast_to(a, u.shape), u)
@@ -84,6 +93,7 @@ def sample_points(cyl: np.ndarray, C: np.ndarray):
     return edge, region, valid
 
 
+@_quiet
 def image_coords(cam, pts: np.ndarray):
     """(x / z + 1/2, y / z + 1/2, z > 0) of (x, y, z) = P [pts; 1]: the nearest
     pixel is the floor of the first two."""
@@ -95,6 +105,7 @@ def image_coords(cam, pts: np.ndarray):
     return h[..., 0] / zs + 0.5, h[..., 1] / zs + 0.5, front
 
 
+@_quiet
 def sample_map(cam, image_map: np.ndarray, pts: np.ndarray) -> np.ndarray:
     """Map value at the nearest pixel of each point [..., 3] (0 behind or outside)."""
     xs, ys, front = image_coords(cam, pts)

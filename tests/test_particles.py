@@ -116,7 +116,8 @@ def test_view_counts(nviews):
 def test_hand_case():
     import json
     import os
-    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "particle_hand_case.json")))
+    with open(os.path.join(os.path.dirname(__file__), "golden", "particle_hand_case.json")) as fh:
+        g = json.load(fh)
     W, H = g["image"]["width"], g["image"]["height"]
     cams = [Cam(W, H, np.asarray(P, np.float32)) for P in g["cameras_P"]]
     vis, hid = g["visible_cylinder"], g["hidden_cylinder"]
@@ -153,6 +154,19 @@ def test_degenerate_cases():
     # beta = 0: uniform weights whatever the scores
     lw, w, _ = run(cams, parts, Sm, Em, beta=0.0)
     np.testing.assert_allclose(w, np.full(8, 1 / 8), rtol=1e-15)
+    # degenerate cylinders (A = B, NaN radius, infinite end point): unmatched
+    bad = parts.copy()
+    bad[0, 2, 3:6] = bad[0, 2, 0:3]
+    bad[1, 7, 7] = np.nan
+    bad[2, 4, 1] = np.inf
+    ones = [np.ones((c.height, c.width), np.float32) for c in cams]
+    lw, w, t = run(cams, bad, ones, ones)
+    want = PT.log_weights(cams, bad, ones, ones)
+    np.testing.assert_allclose(lw, want, rtol=0, atol=LOGW_ATOL)
+    for k in range(len(cams)):
+        se, sr = PT.camera_terms(cams[k], bad, ones[k], ones[k])
+        np.testing.assert_allclose(t[:, k, 0], se, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(t[:, k, 1], sr, rtol=0, atol=1e-13)
     # no views: log w = 0
     plan = psfs.Plan([])
     cyl = torch.from_numpy(parts).cuda()

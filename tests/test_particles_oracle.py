@@ -27,7 +27,8 @@ class Cam:
 
 
 def _hand_case():
-    g = json.load(open(GOLDEN))
+    with open(GOLDEN) as fh:
+        g = json.load(fh)
     W, H = g["image"]["width"], g["image"]["height"]
     cams = [Cam(W, H, np.asarray(P, np.float64)) for P in g["cameras_P"]]
     vis, hid = np.asarray(g["visible_cylinder"]), np.asarray(g["hidden_cylinder"])
@@ -164,6 +165,22 @@ def test_camera_inside_a_cylinder():
     se, sr = PT.camera_terms(cam, parts, ones, ones)
     np.testing.assert_allclose(se, 16 / 160, rtol=1e-14)
     np.testing.assert_allclose(sr, 24 / 240, rtol=1e-14)
+
+
+def test_degenerate_geometry_counts_as_unmatched():
+    """A cylinder with A = B, a NaN radius or an infinite end point has no
+    outline: its 16 outline and 24 silhouette points count p = 0 in every view
+    (here every other point reads 1)."""
+    cams, parts = _visible_scene()
+    parts = parts[:3].astype(np.float64).copy()
+    parts[0, 2, 3:6] = parts[0, 2, 0:3]
+    parts[1, 7, 7] = np.nan
+    parts[2, 4, 1] = np.inf
+    for cam in cams:
+        ones = np.ones((cam.height, cam.width))
+        se, sr = PT.camera_terms(cam, parts, ones, ones)
+        np.testing.assert_allclose(se, 16 / 160, rtol=1e-14)
+        np.testing.assert_allclose(sr, 24 / 240, rtol=1e-14)
 
 
 def test_image_borders():
