@@ -361,10 +361,10 @@ def measure_colour(torch, psfs, slot, frame, timed_graph, args):
         plan.colour(ims, idx, colour=colour, views=views, workspace=ws)
 
     ms = timed_graph([f], max(20, args.steps // 10), 5)
-    npix = frame.npix
-    # algorithmic bytes: the depth buffer cleared (8 B per pixel of every view)
-    # and the list, its pixels and its outputs (small next to the buffer)
-    algo = 8 * npix + n * (4 + 12 + 4)
+    # algorithmic bytes: the list and its outputs (4 + 12 + 4 B per voxel) and,
+    # per (voxel, view), the depth-buffer entry of its pixel cleared, updated
+    # and read (3 x 8 B) and the pixel's RGB (3 B)
+    algo = n * (4 + 12 + 4) + n * frame.n * (3 * 8 + 3)
     print(f"[bench] voxel colour {ms * 1e3:.2f} us ({n} voxels)", file=sys.stderr, flush=True)
     out = {"workload": "colour of the surface voxels of the 128^3 x 8-view frame", "us": ms * 1e3, "voxels": n,
            "algorithmic_bytes": algo, "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}

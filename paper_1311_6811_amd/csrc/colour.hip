@@ -1,7 +1,8 @@
-// Voxel colouring (Sec. 3.1.1; Sec. 3.3.3 "Voxel Projection and Color
-// Computation"): the colour of every listed voxel (normally the surface list)
+// Voxel colouring (Sec. 3.1.1; the voxel projection and colour step of
+// Sec. 3.3.3): the colour of every listed voxel (normally the surface list)
 // from the views that see it. Four launches:
-//   colour_clear_kernel  depth buffers to "empty", colour sums and view counts to 0
+//   colour_clear_kernel  per (voxel, view): the depth-buffer entry of the voxel's
+//                        pixel to "empty"; colour sums and view counts to 0
 //   depth_kernel         per (voxel, view): project as the fusion does and keep
 //                        the nearest voxel of every pixel with a 64-bit atomic
 //                        minimum of (depth bits << 32 | list position)
@@ -50,15 +51,22 @@ __device__ __forceinline__ bool locate(const ColourArgs &a, const ViewGeom &g, i
     return true;
 }
 
+// grid (ceil(nlist / 256), max(views, 1)): the depth-buffer entries the list
+// can reach to "empty" (only those are read later), colour sums and view
+// counts to 0
 __global__ __launch_bounds__(256) void colour_clear_kernel(ColourArgs a)
 {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < a.zbuf_len; t += stride)
-        a.zbuf[t] = kEmpty;
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nlist; t += stride) {
-        a.sums[3 * t] = a.sums[3 * t + 1] = a.sums[3 * t + 2] = 0u;
-        a.views[t] = 0;
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= a.nlist) return;
+    if (blockIdx.y == 0) {
+        a.sums[3 * q] = a.sums[3 * q + 1] = a.sums[3 * q + 2] = 0u;
+        a.views[q] = 0;
     }
+    if (static_cast<int>(blockIdx.y) >= a.n) return;
+    const ViewGeom &g = a.view[blockIdx.y];
+    uint32_t pix;
+    float depth;
+    if (locate(a, g, a.list[q], pix, depth)) a.zbuf[g.map_off + pix] = kEmpty;
 }
 
 // grid (ceil(nlist / 256), views)
@@ -111,19 +119,14 @@ __global__ __launch_bounds__(256) void colour_final_kernel(ColourArgs a)
 
 hipError_t launch_colour(const ColourArgs &a, hipStream_t s)
 {
-    const int64_t fill = a.zbuf_len > a.nlist ? a.zbuf_len : a.nlist;
-    int64_t cb = (fill + 255) / 256;
-    if (cb > 4096) cb = 4096;
-    if (cb < 1) cb = 1;
-    hipLaunchKernelGGL(colour_clear_kernel, dim3(static_cast<unsigned>(cb)), dim3(256), 0, s, a);
-    if (a.nlist > 0) {
-        const unsigned qb = static_cast<unsigned>((a.nlist + 255) / 256);
-        if (a.n > 0) {
-            hipLaunchKernelGGL(depth_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
-            hipLaunchKernelGGL(colour_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
-        }
-        hipLaunchKernelGGL(colour_final_kernel, dim3(qb), dim3(256), 0, s, a);
+    if (a.nlist <= 0) return hipSuccess;
+    const unsigned qb = static_cast<unsigned>((a.nlist + 255) / 256);
+    hipLaunchKernelGGL(colour_clear_kernel, dim3(qb, static_cast<unsigned>(a.n > 0 ? a.n : 1)), dim3(256), 0, s, a);
+    if (a.n > 0) {
+        hipLaunchKernelGGL(depth_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(colour_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
     }
+    hipLaunchKernelGGL(colour_final_kernel, dim3(qb), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
