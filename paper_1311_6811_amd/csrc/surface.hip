@@ -22,59 +22,87 @@
 namespace psfs {
 namespace {
 
-constexpr int kColZ = 8;                            // z-values per lane in smooth_kernel
+constexpr int kTileY = 2;                           // rows per smoothing wave
+constexpr int kTileZ = 2;                           // planes per smoothing wave
 constexpr int kSurfBlock = 4096;                    // voxels per compaction block (16 per lane)
 constexpr int kPerLane = kSurfBlock / 256;
 constexpr int kScanThreads = 1024;
 constexpr int kScanMin = 4096;                      // more blocks: offsets from surface_scan_kernel
 
-// 3x3x3 mean over the in-grid neighbours and threshold. A lane owns kColZ
-// voxels of one (x, y) column: for each plane z it sums the 3 x 3 window of
-// the posterior around (x, y) (rows dy = -1..1, in each row dx = -1..1), then
-// slides a sum of three planes along z; lanes run along x, so each load of the
-// window is one contiguous row of the wave. Out-of-grid cells are skipped and
-// the sum is divided by the number of in-grid cells. One fixed order of the
-// additions for every voxel.
+// 3x3x3 mean over the in-grid neighbours and threshold. A wave owns a tile of
+// 64 x-columns (one per lane) by kTileY rows by kTileZ planes. Per plane it
+// loads the x-windows of the kTileY + 2 rows it needs once (three loads each,
+// a contiguous row of the wave per load), forms each row's 3 x 3 window sum
+// (rows dy = -1..1, in each row dx = -1..1), and slides a sum of three planes
+// along z. Out-of-grid cells are skipped and the sum is divided by the number
+// of in-grid cells; every voxel's additions run in one fixed order.
+template <int TY, int TZ>
 __global__ __launch_bounds__(256) void smooth_kernel(SurfArgs a)
 {
-    const int nxb = (a.nx + 63) / 64;
-    const int64_t col = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    const int64_t ncols = static_cast<int64_t>(nxb) * a.ny;
-    const int zb = static_cast<int>(blockIdx.y);
-    if (col >= ncols) return;
-    const int y = static_cast<int>(col / nxb), x = static_cast<int>(col % nxb) * 64 + static_cast<int>(threadIdx.x & 63);
+    const int nxb = (a.nx + 63) / 64, nyb = (a.ny + TY - 1) / TY;
+    const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= static_cast<int64_t>(nxb) * nyb) return;            // whole waves
+    const int y0 = static_cast<int>(tile / nxb) * TY;
+    const int x = static_cast<int>(tile % nxb) * 64 + static_cast<int>(threadIdx.x & 63);
     if (x >= a.nx) return;
-    const int z0 = zb * kColZ;
+    const int z0 = static_cast<int>(blockIdx.y) * TZ;
     const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
-    const bool xl = x > 0, xr = x + 1 < a.nx, yl = y > 0, yr = y + 1 < a.ny;
-    auto window = [&](int z) -> float {
-        if (z < 0 || z >= a.nz) return 0.0f;
-        const float *row = a.post + z * plane + static_cast<int64_t>(y) * a.nx + x;
-        float s = 0.0f;
+    const bool xl = x > 0, xr = x + 1 < a.nx;
+    // sum of the 3 x 3 window of every output row of the tile in plane z
+    auto windows = [&](int z, float (&w)[TY]) {
+        if (z < 0 || z >= a.nz) {
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            if ((dy < 0 && !yl) || (dy > 0 && !yr)) continue;
-            const float *r = row + dy * a.nx;
-            float t = r[0];
-            if (xl) t = r[-1] + t;
-            if (xr) t = t + r[1];
-            s += t;
+            for (int r = 0; r < TY; ++r) w[r] = 0.0f;
+            return;
         }
-        return s;
+        float row[TY + 2];
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r) {
+            const int y = y0 - 1 + r;
+            row[r] = 0.0f;
+            if (y < 0 || y >= a.ny) continue;
+            const float *p = a.post + z * plane + static_cast<int64_t>(y) * a.nx + x;
+            float t = p[0];
+            if (xl) t = p[-1] + t;
+            if (xr) t = t + p[1];
+            row[r] = t;
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            const int y = y0 + r;
+            float s = 0.0f;
+            if (y > 0) s += row[r];
+            s += row[r + 1];
+            if (y + 1 < a.ny) s += row[r + 2];
+            w[r] = s;
+        }
     };
-    float w[kColZ + 2];
+    float wa[TY], wb[TY], wc[TY];
+    windows(z0 - 1, wa);
+    windows(z0, wb);
+    const int cx = xl + 1 + xr;
 #pragma unroll
-    for (int q = 0; q < kColZ + 2; ++q) w[q] = window(z0 - 1 + q);
-    const int cxy = (xl + 1 + xr) * (yl + 1 + yr);
-#pragma unroll
-    for (int q = 0; q < kColZ; ++q) {
+    for (int q = 0; q < TZ; ++q) {
         const int z = z0 + q;
-        if (z >= a.nz) break;
-        const int c = cxy * ((z > 0) + 1 + (z + 1 < a.nz));
-        const float m = ((w[q] + w[q + 1]) + w[q + 2]) / static_cast<float>(c);
-        const int64_t idx = z * plane + static_cast<int64_t>(y) * a.nx + x;
-        if (a.smoothed) a.smoothed[idx] = m;
-        a.occ[idx] = m > a.tau ? 1 : 0;
+        windows(z + 1, wc);
+        if (z < a.nz) {
+            const int cz = (z > 0) + 1 + (z + 1 < a.nz);
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                const int y = y0 + r;
+                if (y >= a.ny) break;
+                const int c = cx * ((y > 0) + 1 + (y + 1 < a.ny)) * cz;
+                const float m = ((wa[r] + wb[r]) + wc[r]) / static_cast<float>(c);
+                const int64_t idx = z * plane + static_cast<int64_t>(y) * a.nx + x;
+                if (a.smoothed) a.smoothed[idx] = m;
+                a.occ[idx] = m > a.tau ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            wa[r] = wb[r];
+            wb[r] = wc[r];
+        }
     }
 }
 
@@ -258,9 +286,9 @@ hipError_t launch_surface(const SurfArgs &a, hipStream_t s)
         hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, s, a.count);
         return hipGetLastError();
     }
-    const int64_t cols = static_cast<int64_t>((a.nx + 63) / 64) * a.ny;
-    const dim3 sg(static_cast<unsigned>((cols + 3) / 4), static_cast<unsigned>((a.nz + kColZ - 1) / kColZ));
-    hipLaunchKernelGGL(smooth_kernel, sg, dim3(256), 0, s, a);
+    const int64_t tiles = static_cast<int64_t>((a.nx + 63) / 64) * ((a.ny + kTileY - 1) / kTileY);
+    const dim3 sg(static_cast<unsigned>((tiles + 3) / 4), static_cast<unsigned>((a.nz + kTileZ - 1) / kTileZ));
+    hipLaunchKernelGGL((smooth_kernel<kTileY, kTileZ>), sg, dim3(256), 0, s, a);
     hipLaunchKernelGGL(surface_flag_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
     const int scanned = a.nblocks > kScanMin ? 1 : 0;
     if (scanned) hipLaunchKernelGGL(surface_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);
