@@ -8,6 +8,8 @@
 //   surface_flag_kernel    surface flag of every voxel (occupied, with an
 //                          unoccupied or out-of-grid face neighbour) and, per
 //                          block of kSurfBlock consecutive voxels, their count
+//                          (surface_flag_words_kernel: the same, four voxels
+//                          per lane, when rows are whole 4-byte words)
 //   surface_scan_kernel    (grids of more than kScanMin blocks) the block
 //                          offsets: exclusive prefix of the counts, one
 //                          workgroup
@@ -28,6 +30,8 @@ constexpr int kSurfBlock = 4096;                    // voxels per compaction blo
 constexpr int kPerLane = kSurfBlock / 256;
 constexpr int kScanThreads = 1024;
 constexpr int kScanMin = 4096;                      // more blocks: offsets from surface_scan_kernel
+
+__device__ __forceinline__ uint32_t byte_at(uint32_t w, int b) { return (w >> (8 * b)) & 0xffu; }
 
 // 3x3x3 mean over the in-grid neighbours and threshold. A wave owns a tile of
 // 64 x-columns (one per lane) by kTileY rows by kTileZ planes. Per plane it
@@ -149,6 +153,58 @@ __global__ __launch_bounds__(256) void surface_flag_kernel(SurfArgs a)
             ++k;
         }
         k += a.step_k;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) a.counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Surface flags four voxels at a time, when nx is a multiple of 4 and the
+// occupancy and flag arrays are 4-byte aligned: lane l of wave w tests the
+// four voxels of word g = block * 1024 + 256 r + 64 w + l (one row, one
+// plane). Their x-neighbours are in the same word or in the adjacent words of
+// the row, their y- and z-neighbours in the words nx / 4 and nx * ny / 4 away;
+// seven word loads at clamped in-grid addresses (the border tests decide for
+// faces on the grid's border), one word store of four flags.
+__global__ __launch_bounds__(256) void surface_flag_words_kernel(SurfArgs a)
+{
+    __shared__ int part[4];
+    const uint32_t *occ = reinterpret_cast<const uint32_t *>(a.occ);
+    uint32_t *flags = reinterpret_cast<uint32_t *>(a.flags);
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    const int64_t nwords = a.nvox / 4, rw = a.nx / 4, pw = plane / 4;
+    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * (kSurfBlock / 4) + threadIdx.x;
+    int c = 0;
+#pragma unroll
+    for (int r = 0; r < kSurfBlock / 4 / 256; ++r) {
+        const int64_t g = g0 + 256 * r;
+        if (g < nwords) {
+            const int64_t v0 = 4 * g;
+            const int k = static_cast<int>(v0 / plane);
+            const int64_t rem = v0 - static_cast<int64_t>(k) * plane;
+            const int j = static_cast<int>(rem / a.nx), i0 = static_cast<int>(rem - static_cast<int64_t>(j) * a.nx);
+            const uint32_t C = occ[g];
+            const uint32_t L = occ[i0 > 0 ? g - 1 : g], R = occ[i0 + 4 < a.nx ? g + 1 : g];
+            const uint32_t YM = occ[j > 0 ? g - rw : g], YP = occ[j + 1 < a.ny ? g + rw : g];
+            const uint32_t ZM = occ[k > 0 ? g - pw : g], ZP = occ[k + 1 < a.nz ? g + pw : g];
+            const bool border_yz = (j == 0) | (j + 1 == a.ny) | (k == 0) | (k + 1 == a.nz);
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t o = byte_at(C, b);
+                const uint32_t xm = b > 0 ? byte_at(C, b - 1) : byte_at(L, 3);
+                const uint32_t xp = b < 3 ? byte_at(C, b + 1) : byte_at(R, 0);
+                const bool border = border_yz | (b == 0 && i0 == 0) | (b == 3 && i0 + 4 == a.nx);
+                const bool hole = (xm == 0) | (xp == 0) | (byte_at(YM, b) == 0) | (byte_at(YP, b) == 0) |
+                                  (byte_at(ZM, b) == 0) | (byte_at(ZP, b) == 0);
+                const bool surf = (o != 0) & (border | hole);
+                word |= (surf ? 1u : 0u) << (8 * b);
+                c += surf;
+            }
+            flags[g] = word;
+        }
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
@@ -289,7 +345,12 @@ hipError_t launch_surface(const SurfArgs &a, hipStream_t s)
     const int64_t tiles = static_cast<int64_t>((a.nx + 63) / 64) * ((a.ny + kTileY - 1) / kTileY);
     const dim3 sg(static_cast<unsigned>((tiles + 3) / 4), static_cast<unsigned>((a.nz + kTileZ - 1) / kTileZ));
     hipLaunchKernelGGL((smooth_kernel<kTileY, kTileZ>), sg, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(surface_flag_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
+    const bool words = a.nx % 4 == 0 && reinterpret_cast<uintptr_t>(a.occ) % 4 == 0 &&
+                       reinterpret_cast<uintptr_t>(a.flags) % 4 == 0;
+    if (words)
+        hipLaunchKernelGGL(surface_flag_words_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(surface_flag_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a);
     const int scanned = a.nblocks > kScanMin ? 1 : 0;
     if (scanned) hipLaunchKernelGGL(surface_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);
     hipLaunchKernelGGL(surface_write_kernel, dim3(static_cast<unsigned>(a.nblocks)), dim3(256), 0, s, a, scanned);

@@ -67,7 +67,10 @@ def check(post_np, tau=None):
     return len(idx)
 
 
-@pytest.mark.parametrize("shape", [(23, 29, 37), (16, 16, 16), (1, 1, 1), (7, 1, 5), (2, 33, 65), (40, 8, 130)])
+# rows of a multiple of 4 voxels take the four-voxels-per-lane flag kernel,
+# the others the one-voxel kernel
+@pytest.mark.parametrize("shape", [(23, 29, 37), (16, 16, 16), (1, 1, 1), (7, 1, 5), (2, 33, 65), (40, 8, 130),
+                                   (5, 7, 4), (1, 1, 8), (3, 9, 132), (13, 3, 64), (9, 1, 12)])
 def test_random_fields_ragged_grids(shape):
     say(f"surface on {shape}")
     n = check(field(shape, sum(shape)))
