@@ -45,8 +45,8 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
 # those change, traffic is reported as null until the counters are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "b9029a84c7fc9a73f73b2f5b4700c323497eb4eb979de833cd73d09e00372900",
-                 "fetch_kib": 38267.9, "fetch_scale": 2.0, "write_kib": 19912.9, "write_scale": 1.0,
+PIPE_COUNTERS = {"sources_sha256": "08ec1841727e29e9721d9bed94900a1dea30cd705f0d98aba731f111871be83f",
+                 "fetch_kib": 38267.9, "fetch_scale": 2.0, "write_kib": 19909.2, "write_scale": 1.0,
                  "l2_hit_rate": 0.637}
 
 

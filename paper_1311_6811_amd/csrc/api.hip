@@ -606,7 +606,7 @@ int psfs_colour(psfs_plan *plan, const uint8_t *const *images_dev, const int32_t
     a.nlist = count;
     a.zbuf = static_cast<unsigned long long *>(workspace_dev);
     a.zbuf_len = map_floats(plan);
-    a.sums = reinterpret_cast<uint32_t *>(colour_dev);
+    a.colour = colour_dev;
     a.views = views_dev;
     a.nvox = nvox(plan->grid);
     a.n = plan->n;

@@ -1,18 +1,19 @@
 // Voxel colouring (Sec. 3.1.1; the voxel projection and colour step of
 // Sec. 3.3.3): the colour of every listed voxel (normally the surface list)
-// from the views that see it. Four launches:
-//   colour_clear_kernel  per (voxel, view): the depth-buffer entry of the voxel's
-//                        pixel to "empty"; colour sums and view counts to 0
-//   depth_kernel         per (voxel, view): project as the fusion does and keep
-//                        the nearest voxel of every pixel with a 64-bit atomic
-//                        minimum of (depth bits << 32 | list position)
-//   colour_kernel        per (voxel, view): a voxel that holds its pixel adds
-//                        the pixel's RGB to its sums and counts the view
-//   colour_final_kernel  per voxel: sums / count (in place), 0 if unseen
+// from the views that see it. Three launches:
+//   colour_clear_kernel   per (voxel, view): the depth-buffer entry of the
+//                         voxel's pixel to "empty"
+//   depth_kernel          per (voxel, view): project as the fusion does and
+//                         keep the nearest voxel of every pixel with a 64-bit
+//                         atomic minimum of (depth bits << 32 | list position)
+//   colour_gather_kernel  per voxel, one lane per view: a view whose pixel the
+//                         voxel holds contributes the pixel's RGB; the integer
+//                         sums over the views are reduced across the lanes and
+//                         the mean (0 if unseen) and the view count written
 // Depths are positive FP32, whose bit patterns order like the values, so the
 // minimum key is the nearest voxel and, on equal depth, the earlier one in the
-// list. The sums are integers, so the result does not depend on the order of
-// the atomics.
+// list. The sums are integers, so the result does not depend on the order in
+// which they are added.
 #include "kernels_common.h"
 
 namespace psfs {
@@ -51,18 +52,12 @@ __device__ __forceinline__ bool locate(const ColourArgs &a, const ViewGeom &g, i
     return true;
 }
 
-// grid (ceil(nlist / 256), max(views, 1)): the depth-buffer entries the list
-// can reach to "empty" (only those are read later), colour sums and view
-// counts to 0
+// grid (ceil(nlist / 256), views): the depth-buffer entries the list can
+// reach to "empty" (only those are read later)
 __global__ __launch_bounds__(256) void colour_clear_kernel(ColourArgs a)
 {
     const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q >= a.nlist) return;
-    if (blockIdx.y == 0) {
-        a.sums[3 * q] = a.sums[3 * q + 1] = a.sums[3 * q + 2] = 0u;
-        a.views[q] = 0;
-    }
-    if (static_cast<int>(blockIdx.y) >= a.n) return;
     const ViewGeom &g = a.view[blockIdx.y];
     uint32_t pix;
     float depth;
@@ -83,35 +78,47 @@ __global__ __launch_bounds__(256) void depth_kernel(ColourArgs a)
     atomicMin(a.zbuf + g.map_off + pix, key);
 }
 
-__global__ __launch_bounds__(256) void colour_kernel(ColourArgs a)
-{
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= a.nlist) return;
-    const int v = static_cast<int>(blockIdx.y);
-    const ViewGeom &g = a.view[v];
-    uint32_t pix;
-    float depth;
-    if (!locate(a, g, a.list[q], pix, depth)) return;
-    const unsigned long long key =
-        (static_cast<unsigned long long>(__float_as_uint(depth)) << 32) | static_cast<unsigned long long>(q);
-    if (a.zbuf[g.map_off + pix] != key) return;
-    const uint8_t *p = a.img[v] + 3 * static_cast<int64_t>(pix);
-    atomicAdd(a.sums + 3 * q, static_cast<uint32_t>(p[0]));
-    atomicAdd(a.sums + 3 * q + 1, static_cast<uint32_t>(p[1]));
-    atomicAdd(a.sums + 3 * q + 2, static_cast<uint32_t>(p[2]));
-    atomicAdd(a.views + q, 1);
-}
+// grid (ceil(nlist / kGatherVoxels)), block 256: lane group of 16 = one
+// voxel, lane l of the group = view l (idle for l >= n). The sums over the
+// group are integer butterflies within aligned 16-lane groups of the wave.
+constexpr int kGatherLanes = 16;                    // one lane per possible view
+constexpr int kGatherVoxels = 256 / kGatherLanes;   // voxels per workgroup
+static_assert(kGatherLanes >= kMaxViews, "a lane for every view");
 
-__global__ __launch_bounds__(256) void colour_final_kernel(ColourArgs a)
+__global__ __launch_bounds__(256) void colour_gather_kernel(ColourArgs a)
 {
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= a.nlist) return;
-    const int n = a.views[q];
-    float *col = reinterpret_cast<float *>(a.sums + 3 * q);
+    const int v = static_cast<int>(threadIdx.x) % kGatherLanes;
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * kGatherVoxels + static_cast<int>(threadIdx.x) / kGatherLanes;
+    uint32_t r = 0, gr = 0, b = 0, seen = 0;
+    if (q < a.nlist && v < a.n) {
+        const ViewGeom &g = a.view[v];
+        uint32_t pix;
+        float depth;
+        if (locate(a, g, a.list[q], pix, depth)) {
+            const unsigned long long key =
+                (static_cast<unsigned long long>(__float_as_uint(depth)) << 32) | static_cast<unsigned long long>(q);
+            if (a.zbuf[g.map_off + pix] == key) {
+                const uint8_t *p = a.img[v] + 3 * static_cast<int64_t>(pix);
+                r = p[0];
+                gr = p[1];
+                b = p[2];
+                seen = 1;
+            }
+        }
+    }
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        const uint32_t s = a.sums[3 * q + ch];
-        col[ch] = n > 0 ? static_cast<float>(s) / static_cast<float>(n) : 0.0f;
+    for (int d = kGatherLanes / 2; d >= 1; d >>= 1) {
+        r += __shfl_xor(r, d, 64);
+        gr += __shfl_xor(gr, d, 64);
+        b += __shfl_xor(b, d, 64);
+        seen += __shfl_xor(seen, d, 64);
+    }
+    if (v == 0 && q < a.nlist) {
+        const float n = static_cast<float>(seen);
+        a.colour[3 * q] = seen > 0 ? static_cast<float>(r) / n : 0.0f;
+        a.colour[3 * q + 1] = seen > 0 ? static_cast<float>(gr) / n : 0.0f;
+        a.colour[3 * q + 2] = seen > 0 ? static_cast<float>(b) / n : 0.0f;
+        a.views[q] = static_cast<int32_t>(seen);
     }
 }
 
@@ -121,12 +128,12 @@ hipError_t launch_colour(const ColourArgs &a, hipStream_t s)
 {
     if (a.nlist <= 0) return hipSuccess;
     const unsigned qb = static_cast<unsigned>((a.nlist + 255) / 256);
-    hipLaunchKernelGGL(colour_clear_kernel, dim3(qb, static_cast<unsigned>(a.n > 0 ? a.n : 1)), dim3(256), 0, s, a);
     if (a.n > 0) {
+        hipLaunchKernelGGL(colour_clear_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
         hipLaunchKernelGGL(depth_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
-        hipLaunchKernelGGL(colour_kernel, dim3(qb, static_cast<unsigned>(a.n)), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(colour_final_kernel, dim3(qb), dim3(256), 0, s, a);
+    const unsigned gb = static_cast<unsigned>((a.nlist + kGatherVoxels - 1) / kGatherVoxels);
+    hipLaunchKernelGGL(colour_gather_kernel, dim3(gb), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -167,7 +167,7 @@ struct ColourArgs {
     int64_t nlist;
     unsigned long long *zbuf;           // workspace: (depth bits << 32 | position) per pixel
     int64_t zbuf_len;
-    uint32_t *sums;                     // the colour output [nlist][3]: integer sums, then FP32 means
+    float *colour;                      // [nlist][3]: mean RGB over the views that see the voxel
     int32_t *views;                     // [nlist]: number of views that see the voxel
     int64_t nvox;
     int32_t n, nx, ny;

@@ -197,8 +197,8 @@ __global__ __launch_bounds__(256) void surface_flag_words_kernel(SurfArgs a)
                 const uint32_t xm = b > 0 ? byte_at(C, b - 1) : byte_at(L, 3);
                 const uint32_t xp = b < 3 ? byte_at(C, b + 1) : byte_at(R, 0);
                 const bool border = border_yz | (b == 0 && i0 == 0) | (b == 3 && i0 + 4 == a.nx);
-                const bool hole = (xm == 0) | (xp == 0) | (byte_at(YM, b) == 0) | (byte_at(YP, b) == 0) |
-                                  (byte_at(ZM, b) == 0) | (byte_at(ZP, b) == 0);
+                const uint32_t ym = byte_at(YM, b), yp = byte_at(YP, b), zm = byte_at(ZM, b), zp = byte_at(ZP, b);
+                const bool hole = (xm == 0) | (xp == 0) | (ym == 0) | (yp == 0) | (zm == 0) | (zp == 0);
                 const bool surf = (o != 0) & (border | hole);
                 word |= (surf ? 1u : 0u) << (8 * b);
                 c += surf;
