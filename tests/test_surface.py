@@ -172,14 +172,15 @@ def test_largest_workload_256cube_12_views():
     assert n > 5000 and und < 1e-3 * p.size
 
 
-def test_largest_grid_properties():
-    """A 1290^3 grid (just under the 2^31-voxel limit, 524 k compaction blocks):
-    a smooth ball-shaped posterior made on the GPU; checked by properties that
-    hold at any size: the count equals the surface voxels of the returned
-    occupancy (occupied with an unoccupied or out-of-grid face neighbour), the
-    list is ascending and holds exactly those voxels, and sampled smoothed
-    values are the 3x3x3 in-grid means of the posterior."""
-    n = 1290
+@pytest.mark.parametrize("n", [1290, 1288])
+def test_largest_grid_properties(n):
+    """A 1290^3 grid (just under the 2^31-voxel limit, 524 k compaction blocks;
+    rows of 1290 voxels take the one-voxel flag kernel, the 1288^3 grid the
+    four-voxel one): a smooth ball-shaped posterior made on the GPU; checked by
+    properties that hold at any size: the count equals the surface voxels of
+    the returned occupancy (occupied with an unoccupied or out-of-grid face
+    neighbour), the list is ascending and holds exactly those voxels, and
+    sampled smoothed values are the 3x3x3 in-grid means of the posterior."""
     say(f"surface at {n}^3 (properties)")
     ax = torch.arange(n, device="cuda", dtype=torch.float32) / (n - 1) * 2.0 - 1.0
     r2 = ax.view(n, 1, 1) ** 2 + ax.view(1, n, 1) ** 2 + (1.3 * ax).view(1, 1, n) ** 2
