@@ -77,6 +77,26 @@ def test_random_fields_ragged_grids(shape):
     say(f"  {n} surface voxels")
 
 
+def test_unaligned_occupancy_output():
+    """Rows of whole 4-byte words but an occupancy array at an odd address: the
+    one-voxel flag kernel runs and gives the same list as the oracle."""
+    shape = (6, 9, 12)
+    p = field(shape, 77)
+    sm, _, _ = SO.extract(p.astype(np.float64))
+    tau = clear_tau(sm)
+    _, occ_ref, idx = SO.extract(p.astype(np.float64), tau)
+    plan = psfs.Plan(None, grid_of(shape), threshold=tau)
+    post = torch.from_numpy(np.ascontiguousarray(p)).cuda()
+    raw = torch.empty(int(np.prod(shape)) + 1, dtype=torch.uint8, device="cuda")
+    occ = raw[1:].view(shape)
+    assert occ.data_ptr() % 4 == 1
+    res = plan.surface(post, occ=occ)
+    torch.cuda.synchronize()
+    assert np.array_equal(occ.cpu().numpy(), occ_ref)
+    assert int(res.count.item()) == len(idx)
+    assert np.array_equal(res.indices().cpu().numpy().astype(np.int64), idx)
+
+
 def test_posterior_of_the_headline_workload():
     say("surface of the 128^3 x 8-view posterior")
     fr = S.config_frame(1, 0)
