@@ -24,7 +24,12 @@
  *     reports.
  *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *     stream). Every compute call is asynchronous; faults surface at the
- *     caller's synchronisation.
+ *     caller's synchronisation. A plan holds no device state: cameras, grid,
+ *     parameters and buffer addresses are copied into each launch's
+ *     arguments, so one plan may feed work on several streams at once (each
+ *     with its own workspace and outputs), and changing its settings after a
+ *     call does not change work already enqueued. Calls can be captured into
+ *     HIP graphs: no call records a memset.
  *   - Errors: every `int` function returns a psfs_status. Arguments are
  *     validated before anything is enqueued; on an error nothing is enqueued
  *     and psfs_last_error() holds a thread-local message. HIP runtime failures
