@@ -168,6 +168,27 @@ __global__ __launch_bounds__(kNormThreads) void particle_normalise_kernel(NormAr
 {
     __shared__ double red[2][kNormThreads / 64];
     const int t = static_cast<int>(threadIdx.x), lane = t & 63, wave = t >> 6;
+    if (a.np <= kNormThreads) {
+        // one particle per thread: its log weight is read once and its
+        // exponential computed once, for the sum and for its weight
+        const bool has = t < a.np;
+        const double z = has ? a.beta * a.logw[t] : -INFINITY;
+        double mx = z;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        if (lane == 0) red[0][wave] = mx;
+        __syncthreads();
+        double zmax = red[0][0];
+        for (int k = 1; k < kNormThreads / 64; ++k) zmax = fmax(zmax, red[0][k]);
+        const double e = has ? exp(z - zmax) : 0.0;
+        const double sum = wave_sum(e);
+        if (lane == 0) red[1][wave] = sum;
+        __syncthreads();
+        double total = 0.0;
+        for (int k = 0; k < kNormThreads / 64; ++k) total += red[1][k];
+        if (has) a.weights[t] = e / total;
+        return;
+    }
     double mx = -INFINITY;
     for (int64_t i = t; i < a.np; i += kNormThreads) mx = fmax(mx, a.beta * a.logw[i]);
 #pragma unroll

@@ -98,6 +98,23 @@ def test_parity_random_maps_and_beta():
     check(cams, parts, Sm, Em, beta=0.3)
 
 
+@pytest.mark.parametrize("n_particles", [1, 1024, 1025])
+def test_normalisation_at_the_thread_count(n_particles):
+    """Up to 1024 particles the normalisation keeps one particle per thread;
+    beyond, each thread loops over several: both sides of the boundary, and a
+    single particle (weight exactly 1)."""
+    say(f"particle weights, {n_particles} particles, normalisation")
+    cams, parts, Sm, Em = S.tracking_inputs(0, 4, n_particles)
+    plan = psfs.Plan(cams)
+    cyl = torch.from_numpy(np.ascontiguousarray(parts, dtype=np.float32)).cuda()
+    lw, w, _ = plan.particle_weights(cyl, to_dev(Sm), to_dev(Em), beta=0.6)
+    torch.cuda.synchronize()
+    lw, w = lw.cpu().numpy(), w.cpu().numpy()
+    np.testing.assert_allclose(w, PT.normalised(lw, 0.6), rtol=W_RTOL, atol=0)
+    if n_particles == 1:
+        assert w[0] == 1.0
+
+
 @pytest.mark.parametrize("nviews", [1, 3, 5, 12, 16])
 def test_view_counts(nviews):
     """Each view count splits the 80 (cylinder, cross-section) pairs over its
