@@ -174,6 +174,32 @@ int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *p
 int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap_next_dev,
                        const float *lmap_cur_dev, float *posterior_dev, uint8_t *occ_dev, void *stream);
 
+/* The same step for two frames of the sequence at once (frames A and B, e.g.
+ * t and t+1), which share the rig and the background model: one launch
+ * computes the pair maps of the next two frames beside the fusion of the
+ * current two. Pair maps interleave the two frames' maps: the value of pixel p
+ * of view k is at float 2 * (psfs_lmap_offset(k) + p) for frame A and the next
+ * float for frame B (2 * psfs_lmap_floats floats per buffer). Each voxel-view
+ * is projected once for both frames and the background model is read once for
+ * both, so a pair costs less than two single steps; every result is
+ * bit-identical to psfs_likelihood and psfs_fuse of each frame alone.
+ * Nearest sampling only (PSFS_E_ARG otherwise); the fixed tile is 8x32 lanes x
+ * 4 voxels per lane.
+ *   images_a_dev, images_b_dev  n device pointers each of the next two frames,
+ *                   or both NULL: no likelihood part
+ *   lmap2_next_dev  pair maps written by this step, 16-byte aligned
+ *   lmap2_cur_dev   pair maps of the current two frames, from an earlier call;
+ *                   must not overlap lmap2_next_dev
+ *   posterior_a_dev, posterior_b_dev  FP32 [nz][ny][nx] of the current two
+ *                   frames, 16-byte aligned, or both NULL: no fusion part
+ *   occ_a_dev, occ_b_dev  nullable u8 [nz][ny][nx] (NULL without posteriors)
+ * Both parts absent is a no-op. Cameras and grid must be set
+ * (PSFS_E_NOT_READY), and the backgrounds for the likelihood part. */
+int psfs_pipeline_step_pair(psfs_plan *plan, const uint8_t *const *images_a_dev,
+                            const uint8_t *const *images_b_dev, float *lmap2_next_dev,
+                            const float *lmap2_cur_dev, float *posterior_a_dev, uint8_t *occ_a_dev,
+                            float *posterior_b_dev, uint8_t *occ_b_dev, void *stream);
+
 /* occ[i] = posterior[i] > tau for i < nvox (Sec. 2.2.2 thresholding);
  * tau in [0,1]; nvox >= 0. */
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,

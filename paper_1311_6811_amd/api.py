@@ -205,6 +205,27 @@ class Plan:
             cur = _dev(lmap_cur, torch.float32, "lmap_cur")
         L.check(L.lib().psfs_pipeline_step(self._h, ims, nxt, cur, pp, op, _stream()))
 
+    def new_lmap_pair(self) -> torch.Tensor:
+        """Pair-map buffer of two frames (interleaved, see psfs_pipeline_step_pair)."""
+        return torch.empty(max(2 * self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
+
+    def pipeline_step_pair(self, images_a=None, images_b=None, lmap2_next: Optional[torch.Tensor] = None,
+                           lmap2_cur: Optional[torch.Tensor] = None, post_a=None, occ_a=None, post_b=None,
+                           occ_b=None) -> None:
+        """One launch for two frames of the sequence: pair maps of (images_a,
+        images_b) into lmap2_next and the fusion of the pair maps lmap2_cur into
+        (post_a, occ_a) and (post_b, occ_b). Either part may be omitted."""
+        ia = self._images(images_a) if images_a is not None else None
+        ib = self._images(images_b) if images_b is not None else None
+        nxt = _dev(lmap2_next, torch.float32, "lmap2_next") if images_a is not None else None
+        shape = (self.grid.nz, self.grid.ny, self.grid.nx)
+        pa = _dev(post_a, torch.float32, "post_a", shape) if post_a is not None else None
+        pb = _dev(post_b, torch.float32, "post_b", shape) if post_b is not None else None
+        oa = _dev(occ_a, torch.uint8, "occ_a", shape) if occ_a is not None else None
+        ob = _dev(occ_b, torch.uint8, "occ_b", shape) if occ_b is not None else None
+        cur = _dev(lmap2_cur, torch.float32, "lmap2_cur") if (post_a is not None or post_b is not None) else None
+        L.check(L.lib().psfs_pipeline_step_pair(self._h, ia, ib, nxt, cur, pa, oa, pb, ob, _stream()))
+
     # ------------------------------------- smoothing and surface voxels
     def surface_workspace_bytes(self) -> int:
         return int(L.lib().psfs_surface_workspace_bytes(self._h))

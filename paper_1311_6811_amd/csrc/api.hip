@@ -499,6 +499,61 @@ int psfs_pipeline_step(psfs_plan *plan, const uint8_t *const *images_dev, float 
     PSFS_GUARD_END
 }
 
+int psfs_pipeline_step_pair(psfs_plan *plan, const uint8_t *const *images_a_dev, const uint8_t *const *images_b_dev,
+                            float *lmap2_next_dev, const float *lmap2_cur_dev, float *posterior_a_dev,
+                            uint8_t *occ_a_dev, float *posterior_b_dev, uint8_t *occ_b_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_grid(plan);
+    if (rc) return rc;
+    if (plan->params.sampling != PSFS_NEAREST) return fail(PSFS_E_ARG, "two-frame steps use nearest sampling");
+    const bool next = images_a_dev != nullptr || images_b_dev != nullptr;
+    const bool cur = posterior_a_dev != nullptr || posterior_b_dev != nullptr;
+    const int64_t maps = map_floats(plan);
+    if (next) {
+        if (!images_a_dev || !images_b_dev) return fail(PSFS_E_ARG, "both frames' images are needed");
+        if ((rc = need_backgrounds(plan))) return rc;
+        if ((rc = check_images(plan, images_a_dev))) return rc;
+        if ((rc = check_images(plan, images_b_dev))) return rc;
+        if (plan->n > 0 && (!lmap2_next_dev || !aligned(lmap2_next_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap2_next must be a 16-byte aligned device pointer");
+    }
+    if (cur) {
+        if (!posterior_a_dev || !posterior_b_dev) return fail(PSFS_E_ARG, "both frames' posteriors are needed");
+        if (!aligned(posterior_a_dev, 16) || !aligned(posterior_b_dev, 16))
+            return fail(PSFS_E_ARG, "posteriors must be 16-byte aligned");
+        if (plan->n > 0 && (!lmap2_cur_dev || !aligned(lmap2_cur_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap2_cur must be a 16-byte aligned device pointer");
+    } else if (occ_a_dev || occ_b_dev) {
+        return fail(PSFS_E_ARG, "occupancy given without a posterior");
+    }
+    if (next && cur && maps > 0) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(lmap2_next_dev), b0 = reinterpret_cast<uintptr_t>(lmap2_cur_dev);
+        const uintptr_t len = 2 * static_cast<uintptr_t>(maps) * sizeof(float);
+        if (a0 < b0 + len && b0 < a0 + len) return fail(PSFS_E_ARG, "lmap2_next and lmap2_cur overlap");
+    }
+    SlmArgs sa{};
+    PairImages ib{};
+    int64_t max_np = 0;
+    if (next && plan->n > 0) {
+        max_np = fill_slm(plan, images_a_dev, lmap2_next_dev, sa);
+        for (int k = 0; k < plan->n; ++k) ib.img[k] = images_b_dev[k];
+    }
+    FuseArgs fa{};
+    fill_geometry(plan, PSFS_NEAREST, fa);
+    fa.lmap = lmap2_cur_dev;
+    const bool fuse = cur && nvox(plan->grid) > 0;
+    fa.post = fuse ? posterior_a_dev : nullptr;
+    fa.occ = fuse ? occ_a_dev : nullptr;
+    if (sa.n == 0 && !fa.post) return PSFS_OK;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_pipeline_pair(sa, ib, fa, fuse ? posterior_b_dev : nullptr, fuse ? occ_b_dev : nullptr, max_np,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "two-frame pipelined kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
 int psfs_threshold(const float *posterior_dev, int64_t nvox_, float tau, uint8_t *occ_dev, void *stream)
 {
     PSFS_GUARD_BEGIN

@@ -200,6 +200,87 @@ __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *m
     }
 }
 
+// ---- two frames of one rig per pass ------------------------------------------
+// Consecutive frames of a sequence share the cameras and the background model.
+// Their maps are kept interleaved ("pair maps": pixel p of the view whose map
+// starts at map_off holds frame A's log(2*SLM) at float 2*(map_off + p) and
+// frame B's right after), so that one projection and one 8-byte gather per
+// voxel-view serve both frames, and the likelihood of both frames reads the
+// background model once.
+
+// slm_wave for two frames: the means and variances are loaded once; lane l
+// writes pixels p0 + 4l .. p0 + 4l + 3 of both frames with two 16-byte stores.
+__device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_t *img_b, const float *mean,
+                                              const float *var, float *out2, int64_t p0, float k0, SlmStage &st,
+                                              const float *fg)
+{
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
+    const f32x4 *vp = reinterpret_cast<const f32x4 *>(var + 3 * p0);
+    const uint32_t *ia = reinterpret_cast<const uint32_t *>(img_a + 3 * p0);
+    const uint32_t *ib = reinterpret_cast<const uint32_t *>(img_b + 3 * p0);
+    f32x4 m[3], v[3];
+    uint32_t wa[3], wb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        m[r] = __builtin_nontemporal_load(mp + lane + 64 * r);
+        v[r] = __builtin_nontemporal_load(vp + lane + 64 * r);
+        wa[r] = __builtin_nontemporal_load(ia + lane + 64 * r);
+        wb[r] = __builtin_nontemporal_load(ib + lane + 64 * r);
+    }
+    Quad qa, qb;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        st.f[lane + 64 * r] = m[r];
+        st.w[lane + 64 * r] = wa[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        qa.m[r] = st.f[3 * lane + r];
+        qa.w[r] = st.w[3 * lane + r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        st.f[lane + 64 * r] = v[r];
+        st.w[lane + 64 * r] = wb[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        qa.v[r] = st.f[3 * lane + r];
+        qb.w[r] = st.w[3 * lane + r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        qb.m[r] = qa.m[r];
+        qb.v[r] = qa.v[r];
+    }
+    const f32x4 ra = quad_log2slm(qa, quad_k0(qa, k0, fg));
+    const f32x4 rb = quad_log2slm(qb, quad_k0(qb, k0, fg));
+    f32x4 *o = reinterpret_cast<f32x4 *>(out2 + 2 * (p0 + 4 * lane));
+    o[0] = f32x4{ra.x, rb.x, ra.y, rb.y};
+    o[1] = f32x4{ra.z, rb.z, ra.w, rb.w};
+}
+
+// slm_wave_tail for two frames.
+__device__ __forceinline__ void slm_wave_pair_tail(const uint8_t *img_a, const uint8_t *img_b, const float *mean,
+                                                   const float *var, float *out2, int64_t p0, int64_t npix, float k0,
+                                                   const float *fg)
+{
+    const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    for (int64_t t = p; t < p + 4 && t < npix; ++t) {
+        const uint8_t *A = img_a + 3 * t, *B = img_b + 3 * t;
+        const float *mm = mean + 3 * t, *vv = var + 3 * t;
+        const float ka = fg ? k0 - fg[colour_bin(A[0], A[1], A[2])] : k0;
+        const float kb = fg ? k0 - fg[colour_bin(B[0], B[1], B[2])] : k0;
+        out2[2 * t] = log2slm(A[0], A[1], A[2], mm[0], mm[1], mm[2], vv[0], vv[1], vv[2], ka);
+        out2[2 * t + 1] = log2slm(B[0], B[1], B[2], mm[0], mm[1], mm[2], vv[0], vv[1], vv[2], kb);
+    }
+}
+
 // Bilinear sample of a likelihood map at (x0 + fx, y0 + fy); taps outside the
 // image count 0. x0, y0 are integral doubles (possibly far outside the image).
 __device__ __forceinline__ float bilinear_sample(const float *map, int W, int H, double x0, double y0, float fx, float fy)
@@ -430,6 +511,78 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
             const float p = sigmoid_fast(L[kk]);
             post[idx] = p;
             if (occ) occ[idx] = p > tau ? 1 : 0;
+        }
+    }
+}
+
+
+// Eq. 3-9 of fuse_column (nearest sampling) for two frames of one rig at
+// once, from pair maps: each voxel-view is projected once and one 8-byte load
+// brings both frames' values; each frame's logit adds its values in view
+// order, so both posteriors have the bits fuse_column gives each frame alone.
+template <int TX, int KZ, class Views>
+__device__ __forceinline__ void fuse_column_pair(const Views &views, int n, const float *lmap2, const GridDesc &a,
+                                                 int i, int j, int k0, float L0, float tau, float *post_a,
+                                                 uint8_t *occ_a, float *post_b, uint8_t *occ_b)
+{
+    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
+    float Z[KZ], La[KZ], Lb[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        Z[kk] = a.oz + a.h * (static_cast<float>(k0 + kk) + 0.5f);
+        La[kk] = L0;
+        Lb[kk] = L0;
+    }
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int i_lo = i - (lane % TX), j_lo = j - (lane / TX);
+    const uint32_t inside = wave_inside_mask(views, n, a, i_lo, i_lo + TX - 1, j_lo, j_lo + 64 / TX - 1, k0,
+                                             k0 + KZ - 1);
+    for (int v = 0; v < n; ++v) {
+        const ViewGeom &g = views(v);
+        const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+        const float2 *map = reinterpret_cast<const float2 *>(lmap2) + g.map_off;
+        const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+        const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+        const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+        float2 val[KZ];
+        if (inside & (1u << v)) {
+            // every lane lands inside the image: truncation is the floor
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
+                const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
+                const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
+                val[kk] = map[__umul24(y, W) + x];
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float c = fmaf(g.P[10], Z[kk], cx);
+                const float r = __builtin_amdgcn_rcpf(c);
+                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
+                val[kk] = ok ? map[__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)] : make_float2(0.0f, 0.0f);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            La[kk] += val[kk].x;
+            Lb[kk] += val[kk].y;
+        }
+    }
+    if (i >= a.nx || j >= a.ny) return;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    int64_t idx = (static_cast<int64_t>(k0) * a.ny + j) * a.nx + i;
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk, idx += plane) {
+        if (k0 + kk < a.nz) {
+            const float pa = sigmoid_fast(La[kk]), pb = sigmoid_fast(Lb[kk]);
+            post_a[idx] = pa;
+            post_b[idx] = pb;
+            if (occ_a) occ_a[idx] = pa > tau ? 1 : 0;
+            if (occ_b) occ_b[idx] = pb > tau ? 1 : 0;
         }
     }
 }

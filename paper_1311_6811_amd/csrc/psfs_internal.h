@@ -67,6 +67,11 @@ struct FuseArgs {
     float tau;                          // threshold on the posterior
 };
 
+// Frame B's images of a two-frame pass (frame A's travel in SlmArgs).
+struct PairImages {
+    const uint8_t *img[kMaxViews];
+};
+
 // Shape of the pipelined launch (likelihood of the next frame + fusion of
 // the current one).
 struct PipeArgs {
@@ -187,6 +192,12 @@ hipError_t launch_fuse(const FuseArgs &a, int tile, int sampling, hipStream_t s)
 // sa.n == 0: no likelihood part; fa.post == nullptr: no fusion part.
 hipError_t launch_pipeline(const SlmArgs &sa, const FuseArgs &fa, int tile, int sampling, int64_t max_npix,
                            hipStream_t s);
+// Two frames of one rig per launch (nearest sampling, tile 8x32x4): pair maps
+// of the next two frames (sa: frame A's images and the shared background, ib:
+// frame B's images, sa.lmap: pair-map buffer) beside the fusion of the
+// current pair (fa.lmap: pair maps; fa.post/occ: frame A; post_b/occ_b: B).
+hipError_t launch_pipeline_pair(const SlmArgs &sa, const PairImages &ib, const FuseArgs &fa, float *post_b,
+                                uint8_t *occ_b, int64_t max_npix, hipStream_t s);
 int64_t diff_fwd_blocks(int nx, int ny, int nz);
 int64_t diff_bwd_blocks(int nx, int ny, int nz);
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);

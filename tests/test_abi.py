@@ -169,6 +169,38 @@ def test_pipeline_step_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_pipeline_step_pair_validation_without_device(lib):
+    h = _plan(lib)
+    fake, fake2, out = C.c_void_p(0x100000), C.c_void_p(0x200000), C.c_void_p(0x300000)
+    imgs = L.ptr_array([0x100000, 0x100000])
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    step = lib.psfs_pipeline_step_pair
+    assert step(h, imgs, imgs, fake, fake2, out, None, out, None, None) == -3          # grid missing
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert step(h, None, None, None, None, None, None, None, None, None) == 0          # nothing to do
+    assert step(h, imgs, imgs, fake, None, None, None, None, None, None) == -3         # backgrounds missing
+    assert lib.psfs_set_background(h, 0, fake, fake) == 0
+    assert lib.psfs_set_background(h, 1, fake, fake) == 0
+    assert step(h, imgs, None, fake, None, None, None, None, None, None) == -1         # frame B's images
+    assert step(h, imgs, imgs, None, None, None, None, None, None, None) == -1         # no lmap2_next
+    assert step(h, imgs, imgs, C.c_void_p(0x100004), None, None, None, None, None, None) == -1
+    assert step(h, None, None, None, fake, out, None, None, None, None) == -1          # frame B's posterior
+    assert step(h, None, None, None, None, out, None, out, None, None) == -1           # no lmap2_cur
+    assert step(h, None, None, None, fake, C.c_void_p(0x300008), None, out, None, None) == -1
+    assert step(h, None, None, None, None, None, out, None, None, None) == -1          # occupancy without posterior
+    # 2 x 128 floats of pair maps: [0x100000, 0x100400) overlaps a buffer at 0x100300
+    assert step(h, imgs, imgs, fake, C.c_void_p(0x100300), out, None, out, None, None) == -1
+    assert "overlap" in lib.psfs_last_error().decode()
+    p = L.psfs_params()
+    lib.psfs_default_params(C.byref(p))
+    p.sampling = psfs.BILINEAR
+    assert lib.psfs_set_params(h, C.byref(p)) == 0
+    assert step(h, imgs, imgs, fake, None, None, None, None, None, None) == -1         # nearest sampling only
+    lib.psfs_plan_destroy(h)
+
+
 def test_surface_validation_without_device(lib):
     h = _plan(lib)
     fake = C.c_void_p(0x100000)
