@@ -35,7 +35,7 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
                  "gpu_ms_per_frame": 84.845207, "gpu_frames_per_s": 11.79,
                  "speedup_gpu_vs_single_thread_cpu": 399.2868, "speedup_gpu_vs_cpu_tbb": 113.13}
 
-# HBM traffic of one pipe_kernel launch on this workload from two rocprofv3
+# HBM traffic of one pipe_pair_kernel launch on this workload from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
 # dispatches of `bench.py --steps 24 --warmup 6 --no-cpu --no-batch --no-diff
 # --calibrate-copy`), each scaled by what the counter reads for the calibration
@@ -45,9 +45,9 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
 # those change, traffic is reported as null until the counters are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "08ec1841727e29e9721d9bed94900a1dea30cd705f0d98aba731f111871be83f",
-                 "fetch_kib": 38267.9, "fetch_scale": 2.0, "write_kib": 19909.2, "write_scale": 1.0,
-                 "l2_hit_rate": 0.637}
+PIPE_COUNTERS = {"sources_sha256": "f49be8b712c41ee5ac3187bf853a5aa98fb8b3a3ee675ab20ebbfe91e0d00c46",
+                 "fetch_kib": 47880.2, "fetch_scale": 2.0, "write_kib": 40989.4, "write_scale": 1.0,
+                 "l2_hit_rate": 0.703}
 
 
 def sources_sha256() -> str:
@@ -61,7 +61,7 @@ def sources_sha256() -> str:
 
 
 def pipe_traffic():
-    """Measured HBM bytes per pipe_kernel launch, or None if the kernel changed."""
+    """Measured HBM bytes per pipe_pair_kernel launch, or None if the kernel changed."""
     c = PIPE_COUNTERS
     if sources_sha256() != c["sources_sha256"]:
         return None
@@ -234,20 +234,55 @@ def main():
         step(len(slots) - 1)
         step(0)
     torch.cuda.synchronize()
+    single_post0 = s0["post"].clone()
+
+    # ---- the headline step: two frames of the sequence per launch. Consecutive
+    # frames of one rig share the cameras and the background model: pair p
+    # pairs frame p (slot p, its own background) with a further frame rendered
+    # for the same rig; pairs rotate over the slots like single frames do.
+    t0 = time.time()
+    extra = [S.config_frame(1, args.slots + p) for p in range(len(slots))]
+    print(f"[bench] generated {len(extra)} more frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    pairs = []
+    for p, (sl, fe) in enumerate(zip(slots, extra)):
+        pairs.append(dict(plan=sl["plan"], ima=sl["ims"], imb=[torch.from_numpy(i).cuda() for i in fe.images],
+                          pa=sl["post"], oa=sl["occ"], pb=torch.empty_like(sl["post"]), ob=torch.empty_like(sl["occ"])))
+    del extra
+    maps2 = [slots[0]["plan"].new_lmap_pair(), slots[0]["plan"].new_lmap_pair()]
+    torch.cuda.synchronize()
+
+    def pair_step(i):
+        # pair maps of pair i+1 into one buffer, fusion of pair i from the other
+        c, nx = pairs[i % len(pairs)], pairs[(i + 1) % len(pairs)]
+        nx["plan"].pipeline_step_pair(nx["ima"], nx["imb"], maps2[(i + 1) % 2], maps2[i % 2],
+                                      c["pa"], c["oa"], c["pb"], c["ob"])
+
+    with torch.cuda.stream(stream):
+        pair_step(len(pairs) - 1)             # pair maps of pair 0 for the first timed step
+    ms_pair, done_pair = timed(pair_step, steps, args.warmup, graph)
+    print(f"[bench] {done_pair} two-frame steps, {ms_pair * 1e3:.2f} us/step = {ms_pair * 1e3 / 2:.2f} us/frame",
+          file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        pair_step(len(pairs) - 1)
+        pair_step(0)
+    torch.cuda.synchronize()
+    pair_bits_equal = bool(torch.equal(pairs[0]["pa"], single_post0))
     maps = [O.slm(i, m, v) for i, m, v in zip(fr0.images, fr0.mean, fr0.var)]
     ref = O.posterior(fr0.cams, fr0.grid, maps)
     got = s0["post"].cpu().numpy().astype(np.float64)
     un = ref.ncombo == 1
     max_err = float(np.abs(got - ref.post)[un].max())
 
-    # roofline of the step's one kernel (pipe_kernel, one launch per step, so
-    # its average launch duration is the HIP-event time per step above):
-    # algorithmic HBM bytes per launch are the frame's inputs (image + mean +
-    # variance, 27 B/pixel) and outputs (posterior + occupancy, 5 B/voxel); the
-    # likelihood maps are an intermediate
-    step_bytes = 27 * npix + 5 * V
-    dom, dom_bytes = "pipe_kernel", step_bytes
-    achieved = dom_bytes / (ms * 1e-3) / 1e9
+    # rooflines: the kernels of both pipelined steps are one launch per step, so
+    # their average launch durations are the HIP-event times per step above
+    single_bytes = 27 * npix + 5 * V
+    # the headline step's one kernel (pipe_pair_kernel, one launch per step):
+    # algorithmic bytes per launch are both frames' images (2 x 3 B/pixel), the
+    # shared background model read once (24 B/pixel) and both frames' outputs
+    # (2 x 5 B/voxel); the pair maps are an intermediate
+    step_bytes = 30 * npix + 10 * V
+    dom, dom_bytes = "pipe_pair_kernel", step_bytes
+    achieved = dom_bytes / (ms_pair * 1e-3) / 1e9
     traffic = pipe_traffic() if graph else None
 
     surface = measure_surface(torch, psfs, slots[0], timed_graph, args)
@@ -271,35 +306,39 @@ def main():
                "sample": f"{nfr} full frames of the same workload (FP64 C oracle, OpenMP, incl. SLM maps and "
                          f"rounding-ambiguity bounds), {dt:.1f} s"}
 
-    value = vv_per_frame / (ms * 1e-3)
+    value = 2 * vv_per_frame / (ms_pair * 1e-3)
     out = {
         "metric": "voxel-view evals/s + frames/s at 128^3x8 cams; fwd+bwd vs fwd-only at 1e-5",
         "value": value,
         "unit": "voxel-view evals/s",
         "n_gpus": 1,
-        "steps": done,
+        "steps": done_pair,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": ms_pair,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "psfs-forward: 128^3 voxel grid over 2 m, 8 ring views 640x480 f=600, "
-                               "10-ellipsoid body, per-pixel Gaussian background; frame sequence, one launch "
-                               "per frame (maps of frame t+1 beside fusion of frame t)",
-                   "frames_per_step": 1, "slots": len(slots), "graph": graph,
+                               "10-ellipsoid body, per-pixel Gaussian background; frame sequence, two frames "
+                               "of the rig per launch (pair maps of the next two frames beside the fusion of "
+                               "the current two; the two frames share the background model)",
+                   "frames_per_step": 2, "slots": len(pairs), "graph": graph,
                    "voxels": V, "views": n, "pixels": npix},
-        "frames_per_s": 1e3 / ms,
+        "frames_per_s": 2e3 / ms_pair,
+        "single_frame_pipelined_us": ms * 1e3,
         "single_frame_path_us": ms_single * 1e3,
-        "kernels_us": {"pipe_kernel": ms * 1e3, "slm_kernel": ms_l * 1e3, "fuse_kernel": ms_f * 1e3},
+        "pair_bits_equal_single": pair_bits_equal,
+        "kernels_us": {"pipe_pair_kernel": ms_pair * 1e3, "pipe_kernel": ms * 1e3, "slm_kernel": ms_l * 1e3,
+                       "fuse_kernel": ms_f * 1e3},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes,
                      "l2_hit_rate": PIPE_COUNTERS["l2_hit_rate"] if traffic is not None else None},
-        "step_roofline": {"algorithmic_bytes": step_bytes,
-                          "achieved_GBs": step_bytes / (ms * 1e-3) / 1e9,
-                          "frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "single_frame_roofline": {"kernel": "pipe_kernel", "algorithmic_bytes": single_bytes,
+                                  "achieved_GBs": single_bytes / (ms * 1e-3) / 1e9,
+                                  "frac": single_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "parity_max_abs_err": max_err,
         "surface": surface,
         "colour": colour,
