@@ -200,6 +200,35 @@ int psfs_pipeline_step_pair(psfs_plan *plan, const uint8_t *const *images_a_dev,
                             const float *lmap2_cur_dev, float *posterior_a_dev, uint8_t *occ_a_dev,
                             float *posterior_b_dev, uint8_t *occ_b_dev, void *stream);
 
+/* The same step for four frames of the sequence at once (frames 0-3, e.g.
+ * t .. t+3), which share the rig and the background model. Quad maps
+ * interleave the four frames' maps: the value of pixel p of view k for frame f
+ * is at float 4 * (psfs_lmap_offset(k) + p) + f (4 * psfs_lmap_floats floats
+ * per buffer). Each voxel-view is projected once and gathered with one
+ * 16-byte load for the four frames, and the background model is read once for
+ * the four; every result is bit-identical to psfs_likelihood and psfs_fuse of
+ * each frame alone (Eq. 1-2 per pixel, Eq. 3-9 per voxel, Sec. 2.2.2).
+ * Nearest sampling only (PSFS_E_ARG otherwise); the fixed tile is 8x32 lanes x
+ * 4 voxels per lane.
+ *   images_dev      host array of 4*n device pointers, frame-major (frame f,
+ *                   view k at f*n + k), each 4-byte aligned; or NULL: no
+ *                   likelihood part
+ *   lmap4_next_dev  quad maps written by this step, 16-byte aligned
+ *   lmap4_cur_dev   quad maps of the current four frames, from an earlier call;
+ *                   must not overlap lmap4_next_dev
+ *   posterior_dev   host array of 4 device pointers, FP32 [nz][ny][nx] of the
+ *                   current four frames, each 16-byte aligned; or NULL: no
+ *                   fusion part
+ *   occ_dev         NULL, or a host array of 4 nullable u8 [nz][ny][nx]
+ *                   device pointers (must be NULL without posteriors)
+ * Both parts absent is a no-op. Cameras and grid must be set
+ * (PSFS_E_NOT_READY), and the backgrounds for the likelihood part. The host
+ * arrays are read before the call returns; the device buffers belong to the
+ * caller and must stay valid until the enqueued work is done. */
+int psfs_pipeline_step_quad(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap4_next_dev,
+                            const float *lmap4_cur_dev, float *const *posterior_dev,
+                            uint8_t *const *occ_dev, void *stream);
+
 /* occ[i] = posterior[i] > tau for i < nvox (Sec. 2.2.2 thresholding);
  * tau in [0,1]; nvox >= 0. */
 int psfs_threshold(const float *posterior_dev, int64_t nvox, float tau, uint8_t *occ_dev,

@@ -73,6 +73,7 @@ SIGNATURES = {
     "psfs_reconstruct": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
     "psfs_pipeline_step": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, vp, vp]),
     "psfs_pipeline_step_pair": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, vp, vp, vp, vp]),
+    "psfs_pipeline_step_quad": (C.c_int, [vp, C.POINTER(vp), vp, vp, C.POINTER(vp), C.POINTER(vp), vp]),
     "psfs_surface_workspace_bytes": (C.c_size_t, [vp]),
     "psfs_colour_workspace_bytes": (C.c_size_t, [vp]),
     "psfs_foreground_model": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),

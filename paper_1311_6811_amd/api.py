@@ -226,6 +226,37 @@ class Plan:
         cur = _dev(lmap2_cur, torch.float32, "lmap2_cur") if (post_a is not None or post_b is not None) else None
         L.check(L.lib().psfs_pipeline_step_pair(self._h, ia, ib, nxt, cur, pa, oa, pb, ob, _stream()))
 
+    def new_lmap_quad(self) -> torch.Tensor:
+        """Quad-map buffer of four frames (interleaved, see psfs_pipeline_step_quad)."""
+        return torch.empty(max(4 * self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
+
+    def pipeline_step_quad(self, images=None, lmap4_next: Optional[torch.Tensor] = None,
+                           lmap4_cur: Optional[torch.Tensor] = None, posts=None, occs=None) -> None:
+        """One launch for four frames of the sequence: quad maps of the four
+        frames' `images` (a sequence of four per-view image lists) into
+        lmap4_next and the fusion of the quad maps lmap4_cur into the four
+        posteriors `posts` (and occupancies `occs`, or None). Either part may
+        be omitted."""
+        ims = None
+        nxt = None
+        if images is not None:
+            if len(images) != 4:
+                raise ValueError(f"expected the images of 4 frames, got {len(images)}")
+            flat = [p for fr in images for p in self._images(fr)[:self.n]]
+            ims = L.ptr_array(flat)
+            nxt = _dev(lmap4_next, torch.float32, "lmap4_next")
+        pp = op = cur = None
+        if posts is not None:
+            if len(posts) != 4 or (occs is not None and len(occs) != 4):
+                raise ValueError("expected 4 posteriors (and 4 occupancies or None)")
+            shape = (self.grid.nz, self.grid.ny, self.grid.nx)
+            pp = L.ptr_array([_dev(t, torch.float32, f"posts[{f}]", shape) for f, t in enumerate(posts)])
+            if occs is not None:
+                op = L.ptr_array([_dev(t, torch.uint8, f"occs[{f}]", shape) if t is not None else None
+                                  for f, t in enumerate(occs)])
+            cur = _dev(lmap4_cur, torch.float32, "lmap4_cur")
+        L.check(L.lib().psfs_pipeline_step_quad(self._h, ims, nxt, cur, pp, op, _stream()))
+
     # ------------------------------------- smoothing and surface voxels
     def surface_workspace_bytes(self) -> int:
         return int(L.lib().psfs_surface_workspace_bytes(self._h))

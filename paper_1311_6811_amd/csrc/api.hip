@@ -554,6 +554,69 @@ int psfs_pipeline_step_pair(psfs_plan *plan, const uint8_t *const *images_a_dev,
     PSFS_GUARD_END
 }
 
+int psfs_pipeline_step_quad(psfs_plan *plan, const uint8_t *const *images_dev, float *lmap4_next_dev,
+                            const float *lmap4_cur_dev, float *const *posterior_dev, uint8_t *const *occ_dev,
+                            void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_grid(plan);
+    if (rc) return rc;
+    if (plan->params.sampling != PSFS_NEAREST) return fail(PSFS_E_ARG, "four-frame steps use nearest sampling");
+    const bool next = images_dev != nullptr;
+    const bool cur = posterior_dev != nullptr;
+    const int64_t maps = map_floats(plan);
+    const int n = plan->n;
+    if (next) {
+        if ((rc = need_backgrounds(plan))) return rc;
+        for (int f = 0; f < 4; ++f)
+            if ((rc = check_images(plan, images_dev + static_cast<ptrdiff_t>(f) * n))) return rc;
+        if (n > 0 && (!lmap4_next_dev || !aligned(lmap4_next_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap4_next must be a 16-byte aligned device pointer");
+    }
+    if (cur) {
+        for (int f = 0; f < 4; ++f) {
+            if (!posterior_dev[f]) return fail(PSFS_E_ARG, "posterior of frame %d is NULL", f);
+            if (!aligned(posterior_dev[f], 16)) return fail(PSFS_E_ARG, "posterior of frame %d is not 16-byte aligned", f);
+        }
+        if (n > 0 && (!lmap4_cur_dev || !aligned(lmap4_cur_dev, 16)))
+            return fail(PSFS_E_ARG, "lmap4_cur must be a 16-byte aligned device pointer");
+    } else if (occ_dev) {
+        return fail(PSFS_E_ARG, "occupancy given without posteriors");
+    }
+    if (next && cur && maps > 0) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(lmap4_next_dev), b0 = reinterpret_cast<uintptr_t>(lmap4_cur_dev);
+        const uintptr_t len = 4 * static_cast<uintptr_t>(maps) * sizeof(float);
+        if (a0 < b0 + len && b0 < a0 + len) return fail(PSFS_E_ARG, "lmap4_next and lmap4_cur overlap");
+    }
+    SlmArgs sa{};
+    QuadImages qi{};
+    int64_t max_np = 0;
+    if (next && n > 0) {
+        max_np = fill_slm(plan, images_dev, lmap4_next_dev, sa);
+        for (int f = 1; f < 4; ++f)
+            for (int k = 0; k < n; ++k) qi.img[f - 1][k] = images_dev[static_cast<ptrdiff_t>(f) * n + k];
+    }
+    FuseArgs fa{};
+    fill_geometry(plan, PSFS_NEAREST, fa);
+    fa.lmap = lmap4_cur_dev;
+    const bool fuse = cur && nvox(plan->grid) > 0;
+    QuadOut qo{};
+    if (fuse) {
+        fa.post = posterior_dev[0];
+        fa.occ = occ_dev ? occ_dev[0] : nullptr;
+        for (int f = 1; f < 4; ++f) {
+            qo.post[f - 1] = posterior_dev[f];
+            qo.occ[f - 1] = occ_dev ? occ_dev[f] : nullptr;
+        }
+    }
+    if (sa.n == 0 && !fa.post) return PSFS_OK;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_pipeline_quad(sa, qi, fa, qo, max_np, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "four-frame pipelined kernel launch");
+    return PSFS_OK;
+    PSFS_GUARD_END
+}
+
 int psfs_threshold(const float *posterior_dev, int64_t nvox_, float tau, uint8_t *occ_dev, void *stream)
 {
     PSFS_GUARD_BEGIN

@@ -141,6 +141,46 @@ __global__ __launch_bounds__(TX * TY) void pipe_pair_kernel(SlmArgs s, PairImage
     }
 }
 
+// Four frames of one rig per launch, laid out as pipe_pair_kernel with quad
+// maps: the background is read once for four frames' likelihoods, and one
+// projection and one 16-byte gather per voxel-view serve four posteriors.
+template <int TX, int TY, int KZ>
+__global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImages qi, FuseArgs f, PipeArgs p,
+                                                            QuadOut qo)
+{
+    static_assert(TX * TY == 256, "four waves per workgroup");
+    __shared__ SlmStage stage[4];
+    const int round = static_cast<int>(blockIdx.x) / kNumXcd, x = static_cast<int>(blockIdx.x) % kNumXcd;
+    if (round < p.slm_rounds) {
+        const int sb = round * kNumXcd + x;
+        if (sb >= s.n * p.slm_per_view) return;
+        const int v = sb / p.slm_per_view;
+        const SlmView &sv = s.view[v];
+        const int wave = static_cast<int>(threadIdx.x >> 6);
+        const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * 4 + wave) * kWavePixels;
+        float *out4 = s.lmap + 4 * sv.map_off;
+        const uint8_t *const img[4] = {sv.img, qi.img[0][v], qi.img[1][v], qi.img[2][v]};
+        if (p0 + kWavePixels <= sv.npix)
+            slm_wave_quad(img, sv.mean, sv.var, out4, p0, s.k0, stage[wave], s.fg);
+        else if (p0 < sv.npix)
+            slm_wave_quad_tail(img, sv.mean, sv.var, out4, p0, sv.npix, s.k0, s.fg);
+    } else {
+        const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
+        if (tile >= p.fuse_tiles) return;
+        const uint32_t ntx = static_cast<uint32_t>((f.nx + TX - 1) / TX), nty = static_cast<uint32_t>((f.ny + TY - 1) / TY);
+        const uint32_t ntile = ntx * nty, bb = static_cast<uint32_t>(tile);
+        const uint32_t zc = bb / ntile, t = bb - zc * ntile;
+        const uint32_t tyi = t / ntx, txi = t - tyi * ntx;
+        const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
+        const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
+        const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};
+        float *const post[4] = {f.post, qo.post[0], qo.post[1], qo.post[2]};
+        uint8_t *const occ[4] = {f.occ, qo.occ[0], qo.occ[1], qo.occ[2]};
+        fuse_column_quad<TX, KZ>([&](int v) -> const ViewGeom & { return f.view[v]; }, f.n, f.lmap, gd, i, j,
+                                 static_cast<int>(zc) * KZ, f.L0, f.tau, post, occ);
+    }
+}
+
 __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)
 {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -242,6 +282,24 @@ hipError_t launch_pipeline_pair(const SlmArgs &sa, const PairImages &ib, const F
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((pipe_pair_kernel<8, 32, 4>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, sa, ib, fa, p,
                        post_b, occ_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_pipeline_quad(const SlmArgs &sa, const QuadImages &qi, const FuseArgs &fa, const QuadOut &qo,
+                                int64_t max_npix, hipStream_t s)
+{
+    PipeArgs p{};
+    const int64_t per_view = sa.n > 0 ? (max_npix + 4 * kWavePixels - 1) / (4 * kWavePixels) : 0;
+    const int64_t slm_blocks = per_view * sa.n;
+    const int64_t tiles = fa.post ? tile_count_of<8, 32, 4>(fa) : 0;
+    p.slm_per_view = static_cast<int32_t>(per_view);
+    p.slm_rounds = static_cast<int32_t>((slm_blocks + kNumXcd - 1) / kNumXcd);
+    p.fuse_rounds = static_cast<int32_t>((tiles + kNumXcd - 1) / kNumXcd);
+    p.fuse_tiles = tiles;
+    const int64_t blocks = static_cast<int64_t>(p.slm_rounds + p.fuse_rounds) * kNumXcd;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((pipe_quad_kernel<8, 32, 4>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, sa, qi, fa, p,
+                       qo);
     return hipGetLastError();
 }
 

@@ -281,6 +281,100 @@ __device__ __forceinline__ void slm_wave_pair_tail(const uint8_t *img_a, const u
     }
 }
 
+// ---- four frames of one rig per pass -----------------------------------------
+// "Quad maps" interleave four frames' maps the same way: pixel p of the view
+// whose map starts at map_off holds frame f's log(2*SLM) at float
+// 4*(map_off + p) + f, so one 16-byte gather per voxel-view serves all four.
+
+// slm_wave for four frames: the means and variances are loaded once and
+// regrouped once; the four images' words are regrouped one after another
+// through the same LDS words. Lane l writes pixels p0 + 4l .. p0 + 4l + 3 of
+// the four frames with four 16-byte stores.
+__device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], const float *mean, const float *var,
+                                              float *out4, int64_t p0, float k0, SlmStage &st, const float *fg)
+{
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
+    const f32x4 *vp = reinterpret_cast<const f32x4 *>(var + 3 * p0);
+    f32x4 m[3], v[3];
+    uint32_t w[4][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        m[r] = __builtin_nontemporal_load(mp + lane + 64 * r);
+        v[r] = __builtin_nontemporal_load(vp + lane + 64 * r);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const uint32_t *ip = reinterpret_cast<const uint32_t *>(img[f] + 3 * p0);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) w[f][r] = __builtin_nontemporal_load(ip + lane + 64 * r);
+    }
+    Quad q;
+    uint32_t qw[4][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        st.f[lane + 64 * r] = m[r];
+        st.w[lane + 64 * r] = w[0][r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        q.m[r] = st.f[3 * lane + r];
+        qw[0][r] = st.w[3 * lane + r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        st.f[lane + 64 * r] = v[r];
+        st.w[lane + 64 * r] = w[1][r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        q.v[r] = st.f[3 * lane + r];
+        qw[1][r] = st.w[3 * lane + r];
+    }
+#pragma unroll
+    for (int f = 2; f < 4; ++f) {
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 3; ++r) st.w[lane + 64 * r] = w[f][r];
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 3; ++r) qw[f][r] = st.w[3 * lane + r];
+    }
+    wave_lds_sync();
+    f32x4 res[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) q.w[r] = qw[f][r];
+        res[f] = quad_log2slm(q, quad_k0(q, k0, fg));
+    }
+    f32x4 *o = reinterpret_cast<f32x4 *>(out4 + 4 * (p0 + 4 * lane));
+    o[0] = f32x4{res[0].x, res[1].x, res[2].x, res[3].x};
+    o[1] = f32x4{res[0].y, res[1].y, res[2].y, res[3].y};
+    o[2] = f32x4{res[0].z, res[1].z, res[2].z, res[3].z};
+    o[3] = f32x4{res[0].w, res[1].w, res[2].w, res[3].w};
+}
+
+// slm_wave_tail for four frames.
+__device__ __forceinline__ void slm_wave_quad_tail(const uint8_t *const (&img)[4], const float *mean,
+                                                   const float *var, float *out4, int64_t p0, int64_t npix, float k0,
+                                                   const float *fg)
+{
+    const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    for (int64_t t = p; t < p + 4 && t < npix; ++t) {
+        const float *mm = mean + 3 * t, *vv = var + 3 * t;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const uint8_t *I = img[f] + 3 * t;
+            const float kt = fg ? k0 - fg[colour_bin(I[0], I[1], I[2])] : k0;
+            out4[4 * t + f] = log2slm(I[0], I[1], I[2], mm[0], mm[1], mm[2], vv[0], vv[1], vv[2], kt);
+        }
+    }
+}
+
 // Bilinear sample of a likelihood map at (x0 + fx, y0 + fy); taps outside the
 // image count 0. x0, y0 are integral doubles (possibly far outside the image).
 __device__ __forceinline__ float bilinear_sample(const float *map, int W, int H, double x0, double y0, float fx, float fy)
@@ -583,6 +677,82 @@ __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, cons
             post_b[idx] = pb;
             if (occ_a) occ_a[idx] = pa > tau ? 1 : 0;
             if (occ_b) occ_b[idx] = pb > tau ? 1 : 0;
+        }
+    }
+}
+
+// Eq. 3-9 of fuse_column (nearest sampling) for four frames of one rig at
+// once, from quad maps: one projection and one 16-byte load per voxel-view;
+// each frame's logit adds its values in view order, so every posterior has
+// the bits fuse_column gives that frame alone. post[f] / occ[f] are frame f's
+// outputs (occ[f] nullable).
+template <int TX, int KZ, class Views>
+__device__ __forceinline__ void fuse_column_quad(const Views &views, int n, const float *lmap4, const GridDesc &a,
+                                                 int i, int j, int k0, float L0, float tau, float *const (&post)[4],
+                                                 uint8_t *const (&occ)[4])
+{
+    const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
+    const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
+    float Z[KZ], L[KZ][4];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) {
+        Z[kk] = a.oz + a.h * (static_cast<float>(k0 + kk) + 0.5f);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) L[kk][f] = L0;
+    }
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int i_lo = i - (lane % TX), j_lo = j - (lane / TX);
+    const uint32_t inside = wave_inside_mask(views, n, a, i_lo, i_lo + TX - 1, j_lo, j_lo + 64 / TX - 1, k0,
+                                             k0 + KZ - 1);
+    for (int v = 0; v < n; ++v) {
+        const ViewGeom &g = views(v);
+        const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+        const f32x4 *map = reinterpret_cast<const f32x4 *>(lmap4) + g.map_off;
+        const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+        const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+        const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+        f32x4 val[KZ];
+        if (inside & (1u << v)) {
+            // every lane lands inside the image: truncation is the floor
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
+                const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
+                const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
+                val[kk] = map[__umul24(y, W) + x];
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KZ; ++kk) {
+                const float c = fmaf(g.P[10], Z[kk], cx);
+                const float r = __builtin_amdgcn_rcpf(c);
+                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
+                val[kk] = ok ? map[__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)]
+                             : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            L[kk][0] += val[kk].x;
+            L[kk][1] += val[kk].y;
+            L[kk][2] += val[kk].z;
+            L[kk][3] += val[kk].w;
+        }
+    }
+    if (i >= a.nx || j >= a.ny) return;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    int64_t idx = (static_cast<int64_t>(k0) * a.ny + j) * a.nx + i;
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk, idx += plane) {
+        if (k0 + kk < a.nz) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float p = sigmoid_fast(L[kk][f]);
+                post[f][idx] = p;
+                if (occ[f]) occ[f][idx] = p > tau ? 1 : 0;
+            }
         }
     }
 }

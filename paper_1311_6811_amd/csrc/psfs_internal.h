@@ -72,6 +72,18 @@ struct PairImages {
     const uint8_t *img[kMaxViews];
 };
 
+// Frames B, C and D of a four-frame pass (frame A's travel in SlmArgs).
+struct QuadImages {
+    const uint8_t *img[3][kMaxViews];
+};
+
+// Outputs of frames B, C and D of a four-frame pass (frame A's travel in
+// FuseArgs); occ entries are nullable.
+struct QuadOut {
+    float *post[3];
+    uint8_t *occ[3];
+};
+
 // Shape of the pipelined launch (likelihood of the next frame + fusion of
 // the current one).
 struct PipeArgs {
@@ -198,6 +210,10 @@ hipError_t launch_pipeline(const SlmArgs &sa, const FuseArgs &fa, int tile, int 
 // current pair (fa.lmap: pair maps; fa.post/occ: frame A; post_b/occ_b: B).
 hipError_t launch_pipeline_pair(const SlmArgs &sa, const PairImages &ib, const FuseArgs &fa, float *post_b,
                                 uint8_t *occ_b, int64_t max_npix, hipStream_t s);
+// Four frames of one rig per launch, as launch_pipeline_pair with quad maps
+// (four floats per pixel, frame-minor) and frames B-D in qi / qo.
+hipError_t launch_pipeline_quad(const SlmArgs &sa, const QuadImages &qi, const FuseArgs &fa, const QuadOut &qo,
+                                int64_t max_npix, hipStream_t s);
 int64_t diff_fwd_blocks(int nx, int ny, int nz);
 int64_t diff_bwd_blocks(int nx, int ny, int nz);
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);

@@ -201,6 +201,44 @@ def test_pipeline_step_pair_validation_without_device(lib):
     lib.psfs_plan_destroy(h)
 
 
+def test_pipeline_step_quad_validation_without_device(lib):
+    h = _plan(lib)
+    fake, fake2, out = C.c_void_p(0x100000), C.c_void_p(0x200000), C.c_void_p(0x300000)
+    imgs = L.ptr_array([0x100000] * 8)                       # 4 frames x 2 views, frame-major
+    posts = L.ptr_array([0x300000] * 4)
+    cams = (L.psfs_camera * 2)(_cam(8, 6), _cam(5, 3))
+    assert lib.psfs_set_cameras(h, 2, cams) == 0
+    step = lib.psfs_pipeline_step_quad
+    assert step(h, imgs, fake, fake2, posts, None, None) == -3          # grid missing
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert step(h, None, None, None, None, None, None) == 0             # nothing to do
+    assert step(h, imgs, fake, None, None, None, None) == -3            # backgrounds missing
+    assert lib.psfs_set_background(h, 0, fake, fake) == 0
+    assert lib.psfs_set_background(h, 1, fake, fake) == 0
+    holed = L.ptr_array([0x100000] * 7 + [0])                   # frame 3, view 1 missing
+    assert step(h, holed, fake, None, None, None, None) == -1
+    assert "view 1" in lib.psfs_last_error().decode()
+    odd = L.ptr_array([0x100000] * 5 + [0x100002] + [0x100000] * 2)   # frame 2, view 1 misaligned
+    assert step(h, odd, fake, None, None, None, None) == -1
+    assert step(h, imgs, None, None, None, None, None) == -1            # no lmap4_next
+    assert step(h, imgs, C.c_void_p(0x100004), None, None, None, None) == -1
+    assert step(h, None, None, None, L.ptr_array([0x300000] * 3 + [0]), None, None) == -1   # frame 3's posterior
+    assert "frame 3" in lib.psfs_last_error().decode()
+    assert step(h, None, None, None, L.ptr_array([0x300000, 0x300008, 0x300000, 0x300000]), None, None) == -1
+    assert step(h, None, None, None, posts, None, None) == -1           # no lmap4_cur
+    assert step(h, None, None, None, None, posts, None) == -1           # occupancy without posteriors
+    # 4 x 128 floats of quad maps: [0x100000, 0x100800) overlaps a buffer at 0x100700
+    assert step(h, imgs, fake, C.c_void_p(0x100700), posts, None, None) == -1
+    assert "overlap" in lib.psfs_last_error().decode()
+    p = L.psfs_params()
+    lib.psfs_default_params(C.byref(p))
+    p.sampling = psfs.BILINEAR
+    assert lib.psfs_set_params(h, C.byref(p)) == 0
+    assert step(h, imgs, fake, None, None, None, None) == -1            # nearest sampling only
+    lib.psfs_plan_destroy(h)
+
+
 def test_surface_validation_without_device(lib):
     h = _plan(lib)
     fake = C.c_void_p(0x100000)

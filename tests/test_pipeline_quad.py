@@ -1,0 +1,136 @@
+"""Four frames of one rig per launch (psfs_pipeline_step_quad): the quad maps
+interleave the four frames' likelihood maps, and every frame's maps, posterior
+and occupancy must be bit-identical to computing that frame alone; one frame
+of the ragged sequence is also checked against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from synth import scene as S
+from tests.gpu_util import assert_occupancy_parity, assert_posterior_parity, plan_for, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sequence(frames, **kw):
+    ims0, mus, vs = upload(frames[0])
+    plan = plan_for(frames[0], mus, vs, **kw)
+    return plan, [ims0] + [upload(fr)[0] for fr in frames[1:]]
+
+
+def outputs(plan, k=4):
+    g = plan.grid
+    shape = (g.nz, g.ny, g.nx)
+    posts = [torch.full(shape, -1.0, dtype=torch.float32, device="cuda") for _ in range(k)]
+    occs = [torch.full(shape, 7, dtype=torch.uint8, device="cuda") for _ in range(k)]
+    return posts, occs
+
+
+def run_quads(plan, images):
+    """A sequence of a multiple of four frames, four per launch (maps of group
+    k beside the fusion of group k - 1); returns every frame's (posterior,
+    occupancy)."""
+    maps = [plan.new_lmap_quad(), plan.new_lmap_quad()]
+    outs = []
+    ngroups = len(images) // 4
+    for k in range(ngroups + 1):
+        nxt = images[4 * k:4 * k + 4] if k < ngroups else None
+        if k > 0:
+            posts, occs = outputs(plan)
+            plan.pipeline_step_quad(nxt, maps[k % 2] if nxt is not None else None, maps[(k - 1) % 2], posts, occs)
+            outs += list(zip(posts, occs))
+        else:
+            plan.pipeline_step_quad(nxt, maps[0])
+    torch.cuda.synchronize()
+    return outs
+
+
+def assert_frames_match(plan, images, outs):
+    assert len(outs) == len(images)
+    for k, (ims, (post, occ)) in enumerate(zip(images, outs)):
+        p1, o1 = plan.reconstruct(ims)
+        torch.cuda.synchronize()
+        assert torch.equal(p1, post), f"frame {k}: posterior differs"
+        assert torch.equal(o1, occ), f"frame {k}: occupancy differs"
+
+
+def test_quad_maps_and_fusion_equal_single_frames():
+    say("four-frame step, 128^3 x 8 views")
+    frames = [S.config_frame(1, f) for f in range(4)]
+    plan, images = sequence(frames)
+    lm4 = plan.new_lmap_quad()
+    plan.pipeline_step_quad(images, lm4)
+    singles = [plan.likelihood(ims) for ims in images]
+    torch.cuda.synchronize()
+    assert torch.equal(lm4, torch.stack(singles, dim=1).reshape(-1))
+    posts, occs = outputs(plan)
+    plan.pipeline_step_quad(None, None, lm4, posts, occs)
+    refs = [plan.fuse(m) for m in singles]
+    torch.cuda.synchronize()
+    for f in range(4):
+        assert torch.equal(posts[f], refs[f][0]), f"frame {f}: posterior"
+        assert torch.equal(occs[f], refs[f][1]), f"frame {f}: occupancy"
+    # without occupancy outputs, and with only some of them
+    q, _ = outputs(plan)
+    plan.pipeline_step_quad(None, None, lm4, q, None)
+    q2, o2 = outputs(plan)
+    plan.pipeline_step_quad(None, None, lm4, q2, [None, o2[1], None, o2[3]])
+    torch.cuda.synchronize()
+    for f in range(4):
+        assert torch.equal(q[f], posts[f]) and torch.equal(q2[f], posts[f])
+    assert torch.equal(o2[1], occs[1]) and torch.equal(o2[3], occs[3])
+    assert bool((o2[0] == 7).all()) and bool((o2[2] == 7).all())      # untouched
+
+
+def test_quad_sequence_bitwise_equals_single_frames():
+    say("four-frame sequence, 8 frames, 64^3 x 4 views")
+    frames = [S.config_frame(0, f) for f in range(8)]
+    plan, images = sequence(frames)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+
+
+def test_quad_ragged_sequence_foreground_and_oracle():
+    """Ragged grid and odd image sizes (tail waves of the likelihood, partial
+    tiles of the fusion), one frame against the FP64 oracle, then the same
+    sequence with a learned foreground model."""
+    say("four-frame sequence, ragged grid, odd image sizes, oracle, foreground model")
+    rng = np.random.default_rng(41)
+    cams = [S.look_at_camera((4 * np.cos(t), 4 * np.sin(t), 1.2), f, W, H)
+            for t, (f, W, H) in zip((0.3, 1.9, 3.7), ((300, 321, 241), (250, 163, 117), (90, 97, 61)))]
+    grid = S.Grid(37, 29, 23, np.array([-0.9, -0.8, -1.05], np.float32), np.float32(0.047))
+    frames = [S.render_frame(13, f, cams, grid, S.make_body(rng), (13, 0)) for f in range(4)]
+    plan, images = sequence(frames, prior=0.4, threshold=0.55)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+    fr = frames[3]
+    maps = [O.slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
+    ref = O.posterior(fr.cams, fr.grid, maps, 0.4)
+    assert_posterior_parity(outs[3][0], ref, combos=lambda v: O.voxel_combos(fr.cams, fr.grid, maps, v, 0.4))
+    assert_occupancy_parity(outs[3][1], ref, tau=0.55)
+    logd = plan.foreground_model(images[0], lmap=plan.likelihood(images[0]))
+    plan.set_foreground(logd)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+    plan.set_foreground(None)
+
+
+def test_quad_zero_views_give_the_prior():
+    say("four-frame step, no views")
+    fr = S.config_frame(0, 0)
+    plan, _ = sequence([fr])
+    plan.set_cameras([])
+    posts, _ = outputs(plan)
+    plan.pipeline_step_quad([[], [], [], []], plan.new_lmap_quad(), plan.new_lmap_quad(), posts, None)
+    torch.cuda.synchronize()
+    prior = torch.full_like(posts[0], 0.5)
+    for p in posts:
+        assert torch.allclose(p, prior)
