@@ -1,14 +1,16 @@
 """Benchmark of the occupancy pass on one MI355X.
 
-A step reconstructs one frame of the 128^3-voxel, 8-view, 640x480 workload
+A step reconstructs four frames of the 128^3-voxel, 8-view, 640x480 workload
 within a frame sequence: one launch computes the likelihood maps of all views
-of frame t+1 (Eq. 1-2) beside the projection + gather + fusion + posterior +
-threshold of every voxel of frame t (Eq. 3-9), from the maps the previous
-launch wrote. Inputs are resident in HBM before the timed region; frames
-rotate over several independent slots (each with its own images and
-background model) so the working set exceeds the 256 MB Infinity Cache and
-every step streams its inputs from HBM. The two-launch single-frame path
-(likelihood, then fusion) is timed beside it.
+of the next four frames (Eq. 1-2; the four frames share the rig and the
+background model, which is read once for them) beside the projection +
+gather + fusion + posterior + threshold of every voxel of the current four
+frames (Eq. 3-9), from the maps the previous launch wrote. Inputs are
+resident in HBM before the timed region; steps rotate over several
+independent slots (each with its own images and background model) so the
+working set exceeds the 256 MB Infinity Cache and every step streams its
+inputs from HBM. The one-frame and two-frame pipelined steps and the
+two-launch single-frame path (likelihood, then fusion) are timed beside it.
 
 Prints one JSON line (the contract of the driver) with the headline value,
 the dominant kernel's roofline figure and the FP64 CPU oracle's rate.
@@ -35,19 +37,19 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
                  "gpu_ms_per_frame": 84.845207, "gpu_frames_per_s": 11.79,
                  "speedup_gpu_vs_single_thread_cpu": 399.2868, "speedup_gpu_vs_cpu_tbb": 113.13}
 
-# HBM traffic of one pipe_pair_kernel launch on this workload from two rocprofv3
+# HBM traffic of one pipe_quad_kernel launch on this workload from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
 # dispatches of `bench.py --steps 24 --warmup 6 --no-cpu --no-batch --no-diff
 # --calibrate-copy`), each scaled by what the counter reads for the calibration
-# kernel (torch.neg over 256 MiB: FETCH_SIZE 131080 KiB for 262144 KiB read,
+# kernel (torch.neg over 256 MiB: FETCH_SIZE 131081 KiB for 262144 KiB read,
 # x2.0; WRITE_SIZE 262144 KiB for 262144 KiB written, x1.0). The figures hold
 # for the kernel sources they were taken on (SHA-256 of the files below); once
 # those change, traffic is reported as null until the counters are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "f49be8b712c41ee5ac3187bf853a5aa98fb8b3a3ee675ab20ebbfe91e0d00c46",
-                 "fetch_kib": 47880.2, "fetch_scale": 2.0, "write_kib": 40989.4, "write_scale": 1.0,
-                 "l2_hit_rate": 0.703}
+PIPE_COUNTERS = {"sources_sha256": "c470a4b26202b02296a3bdc893ba9199846fa497e571f49e018b4f8c28f7cabc",
+                 "fetch_kib": 90227.1, "fetch_scale": 2.0, "write_kib": 90568.9, "write_scale": 1.0,
+                 "l2_hit_rate": 0.680}
 
 
 def sources_sha256() -> str:
@@ -61,7 +63,7 @@ def sources_sha256() -> str:
 
 
 def pipe_traffic():
-    """Measured HBM bytes per pipe_pair_kernel launch, or None if the kernel changed."""
+    """Measured HBM bytes per pipe_quad_kernel launch, or None if the kernel changed."""
     c = PIPE_COUNTERS
     if sources_sha256() != c["sources_sha256"]:
         return None
