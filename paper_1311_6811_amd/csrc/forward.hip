@@ -40,11 +40,9 @@ __device__ __forceinline__ void fuse_tile(const FuseArgs &a, int64_t b)
 {
     // tile counts are below nx*ny*nz < 2^31: 32-bit arithmetic
     const uint32_t ntx = static_cast<uint32_t>((a.nx + TX - 1) / TX), nty = static_cast<uint32_t>((a.ny + TY - 1) / TY);
-    const uint32_t ntile = ntx * nty;
-    const uint32_t bb = static_cast<uint32_t>(b);
-    const uint32_t zc = bb / ntile;
-    const uint32_t t = bb - zc * ntile;
-    const uint32_t tyi = t / ntx, txi = t - tyi * ntx;
+    const uint32_t nzc = static_cast<uint32_t>((a.nz + KZ - 1) / KZ);
+    uint32_t txi, tyi, zc;
+    octant_tile(static_cast<uint32_t>(b), ntx, nty, nzc, txi, tyi, zc);
     const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
     const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
     const int k0 = static_cast<int>(zc) * KZ;
@@ -130,9 +128,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_pair_kernel(SlmArgs s, PairImage
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
         if (tile >= p.fuse_tiles) return;
         const uint32_t ntx = static_cast<uint32_t>((f.nx + TX - 1) / TX), nty = static_cast<uint32_t>((f.ny + TY - 1) / TY);
-        const uint32_t ntile = ntx * nty, bb = static_cast<uint32_t>(tile);
-        const uint32_t zc = bb / ntile, t = bb - zc * ntile;
-        const uint32_t tyi = t / ntx, txi = t - tyi * ntx;
+        const uint32_t nzc = static_cast<uint32_t>((f.nz + KZ - 1) / KZ);
+        uint32_t txi, tyi, zc;
+        octant_tile(static_cast<uint32_t>(tile), ntx, nty, nzc, txi, tyi, zc);
         const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
         const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
         const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};
@@ -172,9 +170,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImage
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
         if (tile >= p.fuse_tiles) return;
         const uint32_t ntx = static_cast<uint32_t>((f.nx + TX - 1) / TX), nty = static_cast<uint32_t>((f.ny + TY - 1) / TY);
-        const uint32_t ntile = ntx * nty, bb = static_cast<uint32_t>(tile);
-        const uint32_t zc = bb / ntile, t = bb - zc * ntile;
-        const uint32_t tyi = t / ntx, txi = t - tyi * ntx;
+        const uint32_t nzc = static_cast<uint32_t>((f.nz + KZ - 1) / KZ);
+        uint32_t txi, tyi, zc;
+        octant_tile(static_cast<uint32_t>(tile), ntx, nty, nzc, txi, tyi, zc);
         const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
         const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
         const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};

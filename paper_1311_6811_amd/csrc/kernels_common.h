@@ -392,6 +392,34 @@ __device__ __forceinline__ float bilinear_sample(const float *map, int W, int H,
     return fmaf(fy, bot - top, top);
 }
 
+// Tile t of an ntx x nty x nzc tile grid taken octant by octant: the grid is
+// halved along each axis (first halves rounded up), the eight octants follow
+// one another, and each octant's tiles run z-major inside it. With
+// contiguous per-XCD tile ranges (xcd_remap, the pipelined launches), an XCD works on
+// one compact block of the grid (one octant when the tile count splits
+// evenly), whose projections cover smaller image areas than a z-slab of the
+// whole grid. A bijection for every grid shape (empty octants are skipped).
+__device__ __forceinline__ void octant_tile(uint32_t t, uint32_t ntx, uint32_t nty, uint32_t nzc, uint32_t &txi,
+                                            uint32_t &tyi, uint32_t &zc)
+{
+    const uint32_t hx = (ntx + 1) / 2, hy = (nty + 1) / 2, hz = (nzc + 1) / 2;
+    uint32_t o = 0, sx = hx, sy = hy, sz = hz;
+    for (; o < 8; ++o) {
+        sx = (o & 1) ? ntx - hx : hx;
+        sy = (o & 2) ? nty - hy : hy;
+        sz = (o & 4) ? nzc - hz : hz;
+        const uint32_t cnt = sx * sy * sz;
+        if (t < cnt) break;
+        t -= cnt;
+    }
+    const uint32_t plane = sx * sy;
+    const uint32_t lz = t / plane, r = t - lz * plane;
+    const uint32_t ly = r / sx, lx = r - ly * sx;
+    txi = ((o & 1) ? hx : 0) + lx;
+    tyi = ((o & 2) ? hy : 0) + ly;
+    zc = ((o & 4) ? hz : 0) + lz;
+}
+
 // Workgroups are dispatched round-robin over the XCDs; give each XCD one
 // contiguous range of logical blocks (z-slabs of the grid), so that its L2
 // holds one band of rows of every likelihood map.
