@@ -82,6 +82,47 @@ def test_pipeline_step_and_reconstruct():
         assert same(post + occ + maps, ref), f"replay {rep}"
 
 
+def test_two_and_four_frame_steps():
+    say("graph replays: two- and four-frame steps, 64^3 x 4 views")
+    frames = [S.config_frame(0, f) for f in range(4)]
+    ims0, mus, vs = upload(frames[0])
+    plan = plan_for(frames[0], mus, vs)
+    ims = [ims0] + [upload(fr)[0] for fr in frames[1:]]
+    shape = (frames[0].grid.nz, frames[0].grid.ny, frames[0].grid.nx)
+    m2 = [plan.new_lmap_pair(), plan.new_lmap_pair()]
+    m4 = [plan.new_lmap_quad(), plan.new_lmap_quad()]
+    post = [torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(6)]
+    occ = [torch.empty(shape, dtype=torch.uint8, device="cuda") for _ in range(6)]
+
+    def calls():
+        # maps of the later frames into one buffer beside the fusion of the other
+        plan.pipeline_step_pair(ims[2], ims[3], m2[1], m2[0], post[0], occ[0], post[1], occ[1])
+        plan.pipeline_step_pair(ims[0], ims[1], m2[0], m2[1], post[0], occ[0], post[1], occ[1])
+        plan.pipeline_step_quad([ims[3], ims[2], ims[1], ims[0]], m4[1], m4[0], post[2:], occ[2:])
+        plan.pipeline_step_quad(ims, m4[0], m4[1], post[2:], occ[2:])
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.pipeline_step_pair(ims[0], ims[1], m2[0])
+        plan.pipeline_step_quad(ims, m4[0])
+        calls()                      # m2[0] / m4[0] hold frames 0-1 / 0-3 again, as before every replay
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in post + occ + m2 + m4]
+    # the last fusion of each kind is of frames 2,3 (pair) and 3,2,1,0 (quad)
+    singles = [plan.reconstruct(i) for i in ims]
+    torch.cuda.synchronize()
+    assert torch.equal(post[0], singles[2][0]) and torch.equal(post[1], singles[3][0])
+    assert all(torch.equal(post[2 + f], singles[3 - f][0]) for f in range(4))
+    g = capture(calls, stream)
+    for rep in range(REPLAYS):
+        scramble(post + occ)
+        plan.reconstruct(ims[1])                              # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert same(post + occ + m2 + m4, ref), f"replay {rep}"
+
+
 def test_surface_and_foreground_model():
     say("graph replays: surface list and foreground model, 64^3 x 4 views")
     fr = S.config_frame(0, 2)
