@@ -142,10 +142,12 @@ __global__ __launch_bounds__(TX * TY) void pipe_pair_kernel(SlmArgs s, PairImage
 // Four frames of one rig per launch, laid out as pipe_pair_kernel with quad
 // maps: the background is read once for four frames' likelihoods, and one
 // projection and one 16-byte gather per voxel-view serve four posteriors.
-// Launched with 16x16-lane tiles of 4 voxels per lane: a wave covers 16x4
-// columns, whose 16-byte gathers land on fewer map rows than the 8x8
-// columns of the 8x32 tile (57.7 against 63.4 us per launch at 128^3 x 8
-// views; 32x8 58.1, 16x16x2 61.1, 64x4 64.7).
+// Launched with 32x8-lane tiles of 4 voxels per lane: a wave covers 32x2
+// columns, so each frame's u8 occupancy goes out in 32-byte row pieces
+// (16x16 tiles wrote 16-byte pieces, which cost 11.5 MB of partial-line
+// writes per launch at 128^3 x 8 views) and its 16-byte gathers land on
+// fewer map rows than the 8x8 columns of the 8x32 tile (per launch at that
+// size: 32x8 51.7, 16x16 52.5, 16x16x2 53.1, 8x32 56.2 us).
 template <int TX, int TY, int KZ>
 __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImages qi, FuseArgs f, PipeArgs p,
                                                             QuadOut qo)
@@ -293,14 +295,14 @@ hipError_t launch_pipeline_quad(const SlmArgs &sa, const QuadImages &qi, const F
     PipeArgs p{};
     const int64_t per_view = sa.n > 0 ? (max_npix + 4 * kWavePixels - 1) / (4 * kWavePixels) : 0;
     const int64_t slm_blocks = per_view * sa.n;
-    const int64_t tiles = fa.post ? tile_count_of<16, 16, 4>(fa) : 0;
+    const int64_t tiles = fa.post ? tile_count_of<32, 8, 4>(fa) : 0;
     p.slm_per_view = static_cast<int32_t>(per_view);
     p.slm_rounds = static_cast<int32_t>((slm_blocks + kNumXcd - 1) / kNumXcd);
     p.fuse_rounds = static_cast<int32_t>((tiles + kNumXcd - 1) / kNumXcd);
     p.fuse_tiles = tiles;
     const int64_t blocks = static_cast<int64_t>(p.slm_rounds + p.fuse_rounds) * kNumXcd;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((pipe_quad_kernel<16, 16, 4>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, sa, qi, fa, p,
+    hipLaunchKernelGGL((pipe_quad_kernel<32, 8, 4>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, sa, qi, fa, p,
                        qo);
     return hipGetLastError();
 }

@@ -210,7 +210,7 @@ hipError_t launch_pipeline(const SlmArgs &sa, const FuseArgs &fa, int tile, int 
 // current pair (fa.lmap: pair maps; fa.post/occ: frame A; post_b/occ_b: B).
 hipError_t launch_pipeline_pair(const SlmArgs &sa, const PairImages &ib, const FuseArgs &fa, float *post_b,
                                 uint8_t *occ_b, int64_t max_npix, hipStream_t s);
-// Four frames of one rig per launch (nearest sampling, tile 16x16x4), as
+// Four frames of one rig per launch (nearest sampling, tile 32x8x4), as
 // launch_pipeline_pair with quad maps (four floats per pixel, frame-minor) and
 // frames B-D in qi / qo.
 hipError_t launch_pipeline_quad(const SlmArgs &sa, const QuadImages &qi, const FuseArgs &fa, const QuadOut &qo,
