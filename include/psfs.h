@@ -208,8 +208,9 @@ int psfs_pipeline_step_pair(psfs_plan *plan, const uint8_t *const *images_a_dev,
  * 16-byte load for the four frames, and the background model is read once for
  * the four; every result is bit-identical to psfs_likelihood and psfs_fuse of
  * each frame alone (Eq. 1-2 per pixel, Eq. 3-9 per voxel, Sec. 2.2.2).
- * Nearest sampling only (PSFS_E_ARG otherwise); the fixed tile is 32x8 lanes x
- * 4 voxels per lane.
+ * Nearest sampling only (PSFS_E_ARG otherwise), and every view's image below
+ * 2^28 pixels (PSFS_E_RANGE otherwise); the fixed tile is 32x8 lanes x 4
+ * voxels per lane.
  *   images_dev      host array of 4*n device pointers, frame-major (frame f,
  *                   view k at f*n + k), each 4-byte aligned; or NULL: no
  *                   likelihood part

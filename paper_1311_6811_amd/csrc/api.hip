@@ -562,6 +562,9 @@ int psfs_pipeline_step_quad(psfs_plan *plan, const uint8_t *const *images_dev, f
     int rc = need_grid(plan);
     if (rc) return rc;
     if (plan->params.sampling != PSFS_NEAREST) return fail(PSFS_E_ARG, "four-frame steps use nearest sampling");
+    for (int k = 0; k < plan->n; ++k)    // quad maps are gathered with 32-bit byte offsets
+        if (static_cast<int64_t>(plan->cams[k].width) * plan->cams[k].height >= (int64_t(1) << 28))
+            return fail(PSFS_E_RANGE, "view %d: four-frame steps need images below 2^28 pixels", k);
     const bool next = images_dev != nullptr;
     const bool cur = posterior_dev != nullptr;
     const int64_t maps = map_floats(plan);

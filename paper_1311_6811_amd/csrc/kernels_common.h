@@ -735,11 +735,15 @@ __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, cons
     for (int v = 0; v < n; ++v) {
         const ViewGeom &g = views(v);
         const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
-        const f32x4 *map = reinterpret_cast<const f32x4 *>(lmap4) + g.map_off;
+        // raw buffer loads with 32-bit byte offsets (the host takes this path
+        // only when every view's quad map is below 4 GiB); an offset past
+        // the end returns 0, which is what a voxel-view outside its image adds
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(lmap4 + 4 * g.map_off), static_cast<short>(0), static_cast<int>(W * H * 16u), 0x00020000);
         const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
         const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
         const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
-        f32x4 val[KZ];
+        uint32_t off[KZ];
         if (inside & (1u << v)) {
             // every lane lands inside the image: truncation is the floor
 #pragma unroll
@@ -747,7 +751,7 @@ __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, cons
                 const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
                 const uint32_t x = static_cast<uint32_t>(fmaf(g.P[2], Z[kk], ax) * r);
                 const uint32_t y = static_cast<uint32_t>(fmaf(g.P[6], Z[kk], bx) * r);
-                val[kk] = map[__umul24(y, W) + x];
+                off[kk] = (__umul24(y, W) + x) * 16u;
             }
         } else {
 #pragma unroll
@@ -757,10 +761,13 @@ __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, cons
                 const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
                 const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
                 const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
-                val[kk] = ok ? map[__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)]
-                             : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                off[kk] = ok ? (__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)) * 16u : 0xFFFFFFFFu;
             }
         }
+        f32x4 val[KZ];
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk)
+            val[kk] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, static_cast<int>(off[kk]), 0, 0));
 #pragma unroll
         for (int kk = 0; kk < KZ; ++kk) {
             L[kk][0] += val[kk].x;

@@ -236,6 +236,12 @@ def test_pipeline_step_quad_validation_without_device(lib):
     p.sampling = psfs.BILINEAR
     assert lib.psfs_set_params(h, C.byref(p)) == 0
     assert step(h, imgs, fake, None, None, None, None) == -1            # nearest sampling only
+    lib.psfs_default_params(C.byref(p))
+    assert lib.psfs_set_params(h, C.byref(p)) == 0
+    big = (L.psfs_camera * 2)(_cam(8, 6), _cam(16384, 16384))           # 2^28 pixels
+    assert lib.psfs_set_cameras(h, 2, big) == 0
+    assert step(h, None, None, None, posts, None, None) == -2           # quad maps need < 2^28 pixels
+    assert "2^28" in lib.psfs_last_error().decode()
     lib.psfs_plan_destroy(h)
 
 
