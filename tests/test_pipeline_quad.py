@@ -134,3 +134,13 @@ def test_quad_zero_views_give_the_prior():
     prior = torch.full_like(posts[0], 0.5)
     for p in posts:
         assert torch.allclose(p, prior)
+
+
+def test_quad_largest_workload():
+    """The 12-view 1280x720 rig over a 256^3 grid, four frames in one group:
+    every frame bit-identical to the frame alone."""
+    say("four-frame step, 256^3 x 12 views of 1280x720")
+    frames = [S.config_frame(2, f) for f in range(4)]
+    plan, images = sequence(frames)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
