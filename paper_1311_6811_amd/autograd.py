@@ -27,11 +27,17 @@ class OccupancyLoss(torch.autograd.Function):
     def forward(ctx, P, plan, images, labels, sub, *bg):
         n = len(images)
         means, vars_ = bg[:n], bg[n:]
-        Ph = P.detach().to("cpu", torch.float32).numpy().reshape(n, 3, 4)
-        plan.set_cameras([_View(c.width, c.height, Ph[k]) for k, c in enumerate(plan.sizes)])
-        plan.set_backgrounds([m.detach() for m in means], [v.detach() for v in vars_])
+        Ph = P.detach().to("cpu", torch.float32).numpy().reshape(n, 3, 4).copy()
+        cams = [_View(c.width, c.height, Ph[k]) for k, c in enumerate(plan.sizes)]
+        bg_m, bg_v = [m.detach() for m in means], [v.detach() for v in vars_]
+        plan.set_cameras(cams)
+        plan.set_backgrounds(bg_m, bg_v)
         logits, loss, ws = plan.diff_forward(images, labels, sub)
+        # The plan is shared: another forward may re-set its cameras and
+        # backgrounds before this backward runs, so keep this call's own
+        # (host FP32 matrices, the background tensors) and re-set them there.
         ctx.plan, ctx.images, ctx.sub, ctx.ws = plan, images, sub, ws
+        ctx.cams, ctx.bg = cams, (bg_m, bg_v)
         ctx.p_device = P.device
         ctx.save_for_backward(labels, logits)
         return loss
@@ -39,6 +45,8 @@ class OccupancyLoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_loss):
         labels, logits = ctx.saved_tensors
+        ctx.plan.set_cameras(ctx.cams)
+        ctx.plan.set_backgrounds(*ctx.bg)
         gmeans, gvars, gP = ctx.plan.diff_backward(ctx.images, labels, logits, grad_loss, ctx.ws, ctx.sub)
         return (gP.to(ctx.p_device), None, None, None, None, *gmeans, *gvars)
 

@@ -154,3 +154,32 @@ def test_autograd_function_matches_binding_and_oracle():
     check_grads([m.grad.cpu().numpy() for m in mus], [v.grad.cpu().numpy() for v in vs], P.grad.numpy(), ref,
                 "autograd")
     assert float(loss.detach()) == pytest.approx(O.loss(cams, fr.grid, fr.images, fr.mean, fr.var, labels), rel=LOSS_RTOL)
+
+
+def test_autograd_two_forwards_on_one_plan_before_backward():
+    # two losses on one shared plan, with different cameras and backgrounds,
+    # summed before one backward: each backward must use its own forward's
+    # cameras and backgrounds, not whatever the plan holds last
+    fr_a = S.config_frame(0, 1)
+    fr_b = S.config_frame(0, 2)
+    cams_a = S.perturb_cameras(fr_a.cams, seed=(4, 1))
+    cams_b = S.perturb_cameras(fr_b.cams, seed=(4, 2))
+    lab_a = S.gt_occupancy(fr_a.grid, fr_a.body)
+    lab_b = S.gt_occupancy(fr_b.grid, fr_b.body)
+    plan = psfs.DiffPlan(cams_a, fr_a.grid)
+    leaves = []
+    losses = []
+    for fr, cams, lab in ((fr_a, cams_a, lab_a), (fr_b, cams_b, lab_b)):
+        ims, mus, vs = upload(fr)
+        mus = [m.clone().requires_grad_(True) for m in mus]
+        vs = [v.clone().requires_grad_(True) for v in vs]
+        P = torch.tensor(np.stack([c.P for c in cams]), dtype=torch.float32, requires_grad=True)
+        losses.append(psfs.occupancy_loss(P, mus, vs, ims, torch.from_numpy(lab).cuda(), plan))
+        leaves.append((mus, vs, P))
+    (losses[0] + 3.0 * losses[1]).backward()
+    torch.cuda.synchronize()
+    for (fr, cams, lab, gl), (mus, vs, P), name in zip(((fr_a, cams_a, lab_a, 1.0), (fr_b, cams_b, lab_b, 3.0)),
+                                                        leaves, ("first", "second")):
+        ref = O.grad(cams, fr.grid, fr.images, fr.mean, fr.var, lab, grad_loss=gl)
+        check_grads([m.grad.cpu().numpy() for m in mus], [v.grad.cpu().numpy() for v in vs], P.grad.numpy(), ref,
+                    f"{name} of two forwards")
