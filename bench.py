@@ -73,18 +73,139 @@ def pipe_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=600)
-    ap.add_argument("--warmup", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--replays", type=int, default=20, help="timed passes over the steps (median reported)")
     ap.add_argument("--slots", type=int, default=6)
     ap.add_argument("--eager", action="store_true", help="launch every step from Python instead of replaying a HIP graph")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", type=int, default=-1)
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiable fwd / fwd+bwd measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame uneven batch measurement")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 x 12-view 16-frame sequence")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+class Timer:
+    """HIP-event timing of launch sequences on one stream.
+
+    steps(fn, k): fn(0) .. fn(k-1) are captured into one HIP graph (or, with
+    --eager, launched from Python); after `warmup` untimed calls and one
+    untimed pass, `replays` passes are timed one by one with HIP events on
+    the launch stream. Returns the median, minimum and maximum over the
+    passes, in ms per call of fn."""
+
+    def __init__(self, torch, stream, graph, warmup, replays):
+        self.torch, self.stream, self.graph = torch, stream, graph
+        self.warmup, self.replays = warmup, replays
+
+    def steps(self, fn, k, replays=None):
+        torch, st = self.torch, self.stream
+        replays = self.replays if replays is None else replays
+        with torch.cuda.stream(st):
+            for i in range(self.warmup):
+                fn(i)
+            torch.cuda.synchronize()
+            if self.graph:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=st):
+                    for i in range(k):
+                        fn(i)
+                run = g.replay
+            else:
+                def run():
+                    for i in range(k):
+                        fn(i)
+            run()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(replays):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                run()
+                e1.record(st)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) / k)
+            torch.cuda.synchronize()
+        return {"median": float(np.median(ts)), "min": float(min(ts)), "max": float(max(ts))}
+
+    def calls(self, fns, replays=None):
+        """The same for one pass over a list of argument-free calls."""
+        return self.steps(lambda i: fns[i % len(fns)](), len(fns), replays)
+
+
+def measure_bandwidth(torch, stream, mib=1024, reps=20):
+    """Achievable HBM bandwidth on this device: a device-to-device copy of
+    `mib` MiB (bytes read + bytes written over the time) and a streaming read
+    (sum of the same buffer), median of `reps` timed runs each."""
+    n = (mib << 20) // 4
+    src = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    out = {}
+    with torch.cuda.stream(stream):
+        for name, fn, nbytes in (("copy", lambda: dst.copy_(src), 2 * 4 * n),
+                                 ("read", lambda: torch.sum(src), 4 * n)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            out[name + "_GBs"] = nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    out["bytes"] = mib << 20
+    out["how"] = (f"torch copy_ (read + write) and torch.sum (read) over {mib} MiB FP32 buffers, median of "
+                  f"{reps} runs timed with HIP events")
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def measure_cpu(O, frames, vv_per_frame, args):
+    """The FP64 C oracle on the host cores: median of 5 runs at one thread and
+    at all threads (after one warm-up run), on full frames of the workload."""
+    all_threads = O.threads()
+    res = {}
+    for label, th, per_run in (("one_thread", 1, 1), ("all_threads", all_threads, 4)):
+        O.set_threads(th)
+        fr = frames[0]
+        O.reconstruct(fr.cams, fr.grid, fr.images, fr.mean, fr.var)      # warm-up
+        ts = []
+        for r in range(5):
+            t0 = time.perf_counter()
+            for f in range(per_run):
+                fr = frames[(r * per_run + f) % len(frames)]
+                O.reconstruct(fr.cams, fr.grid, fr.images, fr.mean, fr.var)
+            ts.append((time.perf_counter() - t0) / per_run)
+        res[label] = {"threads": th, "s_per_frame": float(np.median(ts)),
+                      "value": vv_per_frame / float(np.median(ts)), "runs": 5, "frames_per_run": per_run}
+    O.set_threads(all_threads)
+    a = res["all_threads"]
+    return {"value": a["value"], "unit": "voxel-view evals/s", "cores": a["threads"], "kind": "oracle",
+            "sample": f"full 128^3 x 8-view frames of the same workload (FP64 C oracle with OpenMP, incl. the "
+                      f"likelihood maps and the rounding-ambiguity bounds): median of 5 runs of "
+                      f"{a['frames_per_run']} frames at {a['threads']} threads and of 5 single frames at one "
+                      f"thread, after a warm-up frame",
+            "one_thread": res["one_thread"], "all_threads": a, "cpu_model": cpu_model(),
+            "host_cores": os.cpu_count()}
 
 
 def main():
@@ -93,6 +214,9 @@ def main():
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the multi-GPU sharding of this pass is a design, not a launch path here.", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0 or args.replays < 1:
+        print("bench.py needs --steps >= 1, --warmup >= 0 and --replays >= 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -103,6 +227,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     psfs.lib()          # fail loudly if the HIP library is missing
+    stream = torch.cuda.Stream()
     if args.calibrate_copy:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -110,238 +235,155 @@ def main():
             torch.neg(src, out=dst)         # elementwise: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
+    bw = measure_bandwidth(torch, stream)
+    print(f"[bench] achievable bandwidth: copy {bw['copy_GBs']:.0f} GB/s, read {bw['read_GBs']:.0f} GB/s",
+          file=sys.stderr, flush=True)
 
     # ------------------------------------------------------------ inputs
+    # slot q: its own background model and a four-frame sequence of the rig
+    # against it (sequence_frame(1, q, t), t = 0..3; frame 0 is config_frame(1, q))
+    from concurrent.futures import ThreadPoolExecutor
     t0 = time.time()
-    frames = [S.config_frame(1, s) for s in range(args.slots)]
-    print(f"[bench] generated {args.slots} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    with ThreadPoolExecutor(8) as ex:
+        seqs = list(ex.map(lambda qt: S.sequence_frame(1, qt[0], qt[1]),
+                           [(q, t) for q in range(args.slots) for t in range(4)]))
+    print(f"[bench] generated {len(seqs)} frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    frames = [seqs[4 * q] for q in range(args.slots)]
     fr0 = frames[0]
     V = fr0.grid.nvox
     npix = fr0.npix
     n = fr0.n
     vv_per_frame = V * n
+    shape = (fr0.grid.nz, fr0.grid.ny, fr0.grid.nx)
     slots = []
-    for fr in frames:
-        ims = [torch.from_numpy(i).cuda() for i in fr.images]
+    for q in range(args.slots):
+        fr = frames[q]
         mus = [torch.from_numpy(m).cuda() for m in fr.mean]
         vs = [torch.from_numpy(v).cuda() for v in fr.var]
         plan = psfs.Plan(fr.cams, fr.grid)
         plan.set_backgrounds(mus, vs)
         if args.tile >= 0:
             plan.set_tile(args.tile)
-        post = torch.empty((fr.grid.nz, fr.grid.ny, fr.grid.nx), dtype=torch.float32, device="cuda")
-        occ = torch.empty_like(post, dtype=torch.uint8)
-        ws = plan.new_workspace()
-        slots.append(dict(plan=plan, ims=ims, mus=mus, vs=vs, post=post, occ=occ, ws=ws))
+        ims = [[torch.from_numpy(i).cuda() for i in seqs[4 * q + t].images] for t in range(4)]
+        posts = [torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(4)]
+        occs = [torch.empty(shape, dtype=torch.uint8, device="cuda") for _ in range(4)]
+        slots.append(dict(plan=plan, ims=ims, mus=mus, vs=vs, posts=posts, occs=occs, ws=plan.new_workspace()))
+    del seqs
     torch.cuda.synchronize()
+    S_ = len(slots)
+    T = Timer(torch, stream, not args.eager, args.warmup, args.replays)
+    K = args.steps
 
-    maps = [slots[0]["plan"].new_lmap(), slots[0]["plan"].new_lmap()]
-    assert len(slots) % 2 == 0, "an even slot count keeps the two map buffers in step with the cycle"
-
-    def step(i):
-        # maps of frame i+1 into one buffer, fusion of frame i from the other;
-        # every slot has the same rig and grid, so slot i+1's plan fuses frame i
-        s, nx = slots[i % len(slots)], slots[(i + 1) % len(slots)]
-        nx["plan"].pipeline_step(nx["ims"], maps[(i + 1) % 2], maps[i % 2], s["post"], s["occ"])
-
-    def single(i):
-        s = slots[i % len(slots)]
-        s["plan"].reconstruct(s["ims"], s["post"], s["occ"], s["ws"])
-
-    def only_lmap(i):
-        s = slots[i % len(slots)]
-        s["plan"].likelihood(s["ims"], s["ws"].view(torch.float32))
-
-    def only_fuse(i):
-        s = slots[i % len(slots)]
-        s["plan"].fuse(s["ws"].view(torch.float32), s["post"], s["occ"])
-
-    stream = torch.cuda.Stream()
-
-    def timed(fn, steps, warmup, graph):
-        """Average ms per call of fn over `steps` calls on one stream."""
-        with torch.cuda.stream(stream):
-            if graph:
-                cyc = len(slots)
-                g = torch.cuda.CUDAGraph()
-                for i in range(cyc):          # warm the allocator/kernels before capture
-                    fn(i)
-                torch.cuda.synchronize()
-                with torch.cuda.graph(g, stream=stream):
-                    for i in range(cyc):
-                        fn(i)
-                reps = max(1, steps // cyc)
-                for _ in range(max(1, warmup // cyc)):
-                    g.replay()
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(reps):
-                    g.replay()
-                e1.record(stream)
-                torch.cuda.synchronize()
-                return e0.elapsed_time(e1) / (reps * cyc), reps * cyc
-            for i in range(warmup):
-                fn(i)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for i in range(steps):
-                fn(i)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / steps, steps
-
-    def timed_graph(fns, reps, warmup):
-        """Average ms of one pass over fns (a cycle of calls) replayed from a graph."""
-        with torch.cuda.stream(stream):
-            for f in fns:
-                f()
-            torch.cuda.synchronize()
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=stream):
-                for f in fns:
-                    f()
-            for _ in range(warmup):
-                g.replay()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                g.replay()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / (reps * len(fns))
-
-    graph = not args.eager
-    steps = (args.steps // len(slots)) * len(slots) if graph else args.steps
-    steps = max(steps, len(slots))
-    with torch.cuda.stream(stream):
-        step(len(slots) - 1)                  # maps of frame 0 for the first timed step
-    ms, done = timed(step, steps, args.warmup, graph)
-    print(f"[bench] {done} pipelined steps, {ms * 1e3:.2f} us/step", file=sys.stderr, flush=True)
-    ms_single, _ = timed(single, steps, args.warmup, graph)
-    print(f"[bench] single-frame path (two launches) {ms_single * 1e3:.2f} us/frame", file=sys.stderr, flush=True)
-    # the two kernels of the single-frame path alone (HIP events on the launch
-    # stream around graph replays of back-to-back launches)
-    ms_l, _ = timed(only_lmap, steps, args.warmup, graph)
-    ms_f, _ = timed(only_fuse, steps, args.warmup, graph)
-    print(f"[bench] likelihood alone {ms_l * 1e3:.2f} us, fusion alone {ms_f * 1e3:.2f} us",
-          file=sys.stderr, flush=True)
-
-    # parity spot check of the timed configuration on sampled voxels
-    from oracle import oracle as O
-    s0 = slots[0]
-    with torch.cuda.stream(stream):
-        step(len(slots) - 1)
-        step(0)
-    torch.cuda.synchronize()
-    single_post0 = s0["post"].clone()
-
-    # ---- the headline step: two frames of the sequence per launch. Consecutive
-    # frames of one rig share the cameras and the background model: pair p
-    # pairs frame p (slot p, its own background) with a further frame rendered
-    # for the same rig; pairs rotate over the slots like single frames do.
-    t0 = time.time()
-    extra = [S.config_frame(1, args.slots + p) for p in range(len(slots))]
-    print(f"[bench] generated {len(extra)} more frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    pairs = []
-    for p, (sl, fe) in enumerate(zip(slots, extra)):
-        pairs.append(dict(plan=sl["plan"], ima=sl["ims"], imb=[torch.from_numpy(i).cuda() for i in fe.images],
-                          pa=sl["post"], oa=sl["occ"], pb=torch.empty_like(sl["post"]), ob=torch.empty_like(sl["occ"])))
-    del extra
-    maps2 = [slots[0]["plan"].new_lmap_pair(), slots[0]["plan"].new_lmap_pair()]
-    torch.cuda.synchronize()
-
-    def pair_step(i):
-        # pair maps of pair i+1 into one buffer, fusion of pair i from the other
-        c, nx = pairs[i % len(pairs)], pairs[(i + 1) % len(pairs)]
-        nx["plan"].pipeline_step_pair(nx["ima"], nx["imb"], maps2[(i + 1) % 2], maps2[i % 2],
-                                      c["pa"], c["oa"], c["pb"], c["ob"])
-
-    with torch.cuda.stream(stream):
-        pair_step(len(pairs) - 1)             # pair maps of pair 0 for the first timed step
-    ms_pair, done_pair = timed(pair_step, steps, args.warmup, graph)
-    print(f"[bench] {done_pair} two-frame steps, {ms_pair * 1e3:.2f} us/step = {ms_pair * 1e3 / 2:.2f} us/frame",
-          file=sys.stderr, flush=True)
-    with torch.cuda.stream(stream):
-        pair_step(len(pairs) - 1)
-        pair_step(0)
-    torch.cuda.synchronize()
-    pair_bits_equal = bool(torch.equal(pairs[0]["pa"], single_post0))
-
-    # ---- the headline step: four frames of the sequence per launch. Group q
-    # is pair q's two frames and two further frames of the same rig and
-    # background; groups rotate over the slots like pairs do.
-    t0 = time.time()
-    extra = [S.config_frame(1, 2 * args.slots + e) for e in range(2 * len(pairs))]
-    print(f"[bench] generated {len(extra)} more frames in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    quads = []
-    for q, pr in enumerate(pairs):
-        more = [[torch.from_numpy(i).cuda() for i in extra[2 * q + e].images] for e in range(2)]
-        quads.append(dict(plan=pr["plan"], ims=[pr["ima"], pr["imb"]] + more,
-                          posts=[pr["pa"], pr["pb"], torch.empty_like(pr["pa"]), torch.empty_like(pr["pa"])],
-                          occs=[pr["oa"], pr["ob"], torch.empty_like(pr["oa"]), torch.empty_like(pr["oa"])]))
-    del extra
+    # ---- headline: four frames of a slot's sequence per launch. Step i
+    # computes the quad maps of slot i+1's four frames into one buffer beside
+    # the fusion of slot i's four frames from the other.
     maps4 = [slots[0]["plan"].new_lmap_quad(), slots[0]["plan"].new_lmap_quad()]
-    torch.cuda.synchronize()
 
     def quad_step(i):
-        # quad maps of group i+1 into one buffer, fusion of group i from the other
-        c, nx = quads[i % len(quads)], quads[(i + 1) % len(quads)]
+        c, nx = slots[i % S_], slots[(i + 1) % S_]
         nx["plan"].pipeline_step_quad(nx["ims"], maps4[(i + 1) % 2], maps4[i % 2], c["posts"], c["occs"])
 
     with torch.cuda.stream(stream):
-        quad_step(len(quads) - 1)             # quad maps of group 0 for the first timed step
-    ms_quad, done_quad = timed(quad_step, steps, args.warmup, graph)
-    print(f"[bench] {done_quad} four-frame steps, {ms_quad * 1e3:.2f} us/step = {ms_quad * 1e3 / 4:.2f} us/frame",
+        quad_step(S_ - 1)                     # quad maps of slot 0 for the first step
+    t_quad = T.steps(quad_step, K)
+    ms_quad = t_quad["median"]
+    print(f"[bench] {K} four-frame steps x {args.replays} passes: median {ms_quad * 1e3:.2f} us/step "
+          f"(min {t_quad['min'] * 1e3:.2f}, max {t_quad['max'] * 1e3:.2f}) = {ms_quad * 1e3 / 4:.2f} us/frame",
           file=sys.stderr, flush=True)
+
+    # ---- two frames per launch (frames 0 and 1 of each slot's sequence)
+    maps2 = [slots[0]["plan"].new_lmap_pair(), slots[0]["plan"].new_lmap_pair()]
+
+    def pair_step(i):
+        c, nx = slots[i % S_], slots[(i + 1) % S_]
+        nx["plan"].pipeline_step_pair(nx["ims"][0], nx["ims"][1], maps2[(i + 1) % 2], maps2[i % 2],
+                                      c["posts"][0], c["occs"][0], c["posts"][1], c["occs"][1])
+
     with torch.cuda.stream(stream):
-        quad_step(len(quads) - 1)
+        pair_step(S_ - 1)
+    t_pair = T.steps(pair_step, K)
+    ms_pair = t_pair["median"]
+    print(f"[bench] two-frame step {ms_pair * 1e3:.2f} us = {ms_pair * 1e3 / 2:.2f} us/frame",
+          file=sys.stderr, flush=True)
+
+    # ---- one frame per launch, and the two-launch single-frame path
+    maps1 = [slots[0]["plan"].new_lmap(), slots[0]["plan"].new_lmap()]
+
+    def step(i):
+        c, nx = slots[i % S_], slots[(i + 1) % S_]
+        nx["plan"].pipeline_step(nx["ims"][0], maps1[(i + 1) % 2], maps1[i % 2], c["posts"][0], c["occs"][0])
+
+    def single(i):
+        s = slots[i % S_]
+        s["plan"].reconstruct(s["ims"][0], s["posts"][0], s["occs"][0], s["ws"])
+
+    def only_lmap(i):
+        s = slots[i % S_]
+        s["plan"].likelihood(s["ims"][0], s["ws"].view(torch.float32))
+
+    def only_fuse(i):
+        s = slots[i % S_]
+        s["plan"].fuse(s["ws"].view(torch.float32), s["posts"][0], s["occs"][0])
+
+    with torch.cuda.stream(stream):
+        step(S_ - 1)
+    t_one = T.steps(step, K)
+    t_single = T.steps(single, K)
+    t_l = T.steps(only_lmap, K)
+    t_f = T.steps(only_fuse, K)
+    ms, ms_single, ms_l, ms_f = t_one["median"], t_single["median"], t_l["median"], t_f["median"]
+    print(f"[bench] one-frame step {ms * 1e3:.2f} us; two-launch frame {ms_single * 1e3:.2f} us "
+          f"(likelihood {ms_l * 1e3:.2f}, fusion {ms_f * 1e3:.2f})", file=sys.stderr, flush=True)
+
+    # ---- bits: every multi-frame step reproduces the single-frame posteriors
+    from oracle import oracle as O
+    s0 = slots[0]
+    singles = []
+    for t in range(4):
+        p, _ = s0["plan"].reconstruct(s0["ims"][t])
+        singles.append(p)
+    with torch.cuda.stream(stream):
+        quad_step(S_ - 1)
         quad_step(0)
     torch.cuda.synchronize()
-    quad_bits_equal = bool(torch.equal(quads[0]["posts"][0], single_post0))
+    quad_bits_equal = all(bool(torch.equal(s0["posts"][t], singles[t])) for t in range(4))
+    with torch.cuda.stream(stream):
+        pair_step(S_ - 1)
+        pair_step(0)
+    torch.cuda.synchronize()
+    pair_bits_equal = all(bool(torch.equal(s0["posts"][t], singles[t])) for t in range(2))
+    with torch.cuda.stream(stream):
+        step(S_ - 1)
+        step(0)
+    torch.cuda.synchronize()
+    one_bits_equal = bool(torch.equal(s0["posts"][0], singles[0]))
     maps = [O.slm(i, m, v) for i, m, v in zip(fr0.images, fr0.mean, fr0.var)]
     ref = O.posterior(fr0.cams, fr0.grid, maps)
-    got = s0["post"].cpu().numpy().astype(np.float64)
+    got = s0["posts"][0].cpu().numpy().astype(np.float64)
     un = ref.ncombo == 1
     max_err = float(np.abs(got - ref.post)[un].max())
+    del singles
 
-    # rooflines: the kernels of both pipelined steps are one launch per step, so
-    # their average launch durations are the HIP-event times per step above
+    # rooflines: each pipelined step is one launch, so its average launch
+    # duration is the HIP-event time per step above
     single_bytes = 27 * npix + 5 * V
-    # the two-frame step's kernel (pipe_pair_kernel, one launch per step):
-    # algorithmic bytes per launch are both frames' images (2 x 3 B/pixel), the
-    # shared background model read once (24 B/pixel) and both frames' outputs
-    # (2 x 5 B/voxel); the pair maps are an intermediate
+    # two frames per launch: both frames' images (2 x 3 B/pixel), the shared
+    # background model read once (24 B/pixel), both frames' outputs (2 x 5 B/voxel)
     pair_bytes = 30 * npix + 10 * V
-    # the headline step's one kernel (pipe_quad_kernel): four frames' images
-    # (4 x 3 B/pixel), the background once (24 B/pixel), four frames' outputs
+    # four frames per launch (pipe_quad_kernel): four images, the background
+    # once, four frames' outputs; the quad maps are an intermediate
     step_bytes = 36 * npix + 20 * V
     dom, dom_bytes = "pipe_quad_kernel", step_bytes
     achieved = dom_bytes / (ms_quad * 1e-3) / 1e9
-    traffic = pipe_traffic() if graph else None
+    traffic = pipe_traffic() if not args.eager else None
 
-    surface = measure_surface(torch, psfs, slots[0], timed_graph, args)
-    colour = measure_colour(torch, psfs, slots[0], frames[0], timed_graph, args)
-    particles = measure_particles(torch, psfs, S, timed_graph, args)
-    diff = None if args.no_diff else measure_diff(torch, psfs, S, timed_graph, args)
+    c2 = None if args.no_c2 else measure_c2(torch, psfs, S, T, bw, args)
+    surface = measure_surface(torch, psfs, s0, T, args)
+    colour = measure_colour(torch, psfs, s0, fr0, T, args)
+    particles = measure_particles(torch, psfs, S, T, args)
+    diff = None if args.no_diff else measure_diff(torch, psfs, S, T, args)
     batch = None if args.no_batch else measure_batch(torch, psfs, S, args)
-
-    # CPU oracle on a bounded sample of the same workload
-    cpu = None
-    if not args.no_cpu:
-        t0 = time.time()
-        nfr = 0
-        while nfr < 1 or (time.time() - t0 < args.cpu_seconds and nfr < 400):
-            fr = frames[nfr % len(frames)]
-            O.reconstruct(fr.cams, fr.grid, fr.images, fr.mean, fr.var)
-            nfr += 1
-        dt = time.time() - t0
-        cpu = {"value": nfr * vv_per_frame / dt, "unit": "voxel-view evals/s", "cores": O.threads(),
-               "kind": "oracle",
-               "sample": f"{nfr} full frames of the same workload (FP64 C oracle, OpenMP, incl. SLM maps and "
-                         f"rounding-ambiguity bounds), {dt:.1f} s"}
+    cpu = None if args.no_cpu else measure_cpu(O, frames, vv_per_frame, args)
 
     value = 4 * vv_per_frame / (ms_quad * 1e-3)
     out = {
@@ -349,7 +391,7 @@ def main():
         "value": value,
         "unit": "voxel-view evals/s",
         "n_gpus": 1,
-        "steps": done_quad,
+        "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms_quad,
         "higher_is_better": True,
@@ -358,30 +400,42 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "psfs-forward: 128^3 voxel grid over 2 m, 8 ring views 640x480 f=600, "
-                               "10-ellipsoid body, per-pixel Gaussian background; frame sequence, four frames "
-                               "of the rig per launch (quad maps of the next four frames beside the fusion of "
-                               "the current four; the four frames share the background model)",
-                   "frames_per_step": 4, "slots": len(quads), "graph": graph,
+                               "10-ellipsoid body, per-pixel Gaussian background; frame sequences of one rig "
+                               "and background, four frames per launch (quad maps of the next four frames "
+                               "beside the fusion of the current four)",
+                   "frames_per_step": 4, "slots": S_, "graph": not args.eager,
                    "voxels": V, "views": n, "pixels": npix},
+        "timing": {"replays": args.replays, "steps_per_replay": K,
+                   "ms_per_step_median": ms_quad, "ms_per_step_min": t_quad["min"],
+                   "ms_per_step_max": t_quad["max"],
+                   "how": "one HIP graph of exactly `steps` launches, timed pass by pass with HIP events on "
+                          "its stream; median over the passes"},
         "frames_per_s": 4e3 / ms_quad,
-        "two_frame_step_us": ms_pair * 1e3,
-        "quad_bits_equal_single": quad_bits_equal,
-        "single_frame_pipelined_us": ms * 1e3,
-        "single_frame_path_us": ms_single * 1e3,
-        "pair_bits_equal_single": pair_bits_equal,
-        "kernels_us": {"pipe_quad_kernel": ms_quad * 1e3, "pipe_pair_kernel": ms_pair * 1e3, "pipe_kernel": ms * 1e3, "slm_kernel": ms_l * 1e3,
-                       "fuse_kernel": ms_f * 1e3},
+        "bandwidth": bw,
+        "kernels_us": {"pipe_quad_kernel": ms_quad * 1e3, "pipe_pair_kernel": ms_pair * 1e3,
+                       "pipe_kernel": ms * 1e3, "slm_kernel": ms_l * 1e3, "fuse_kernel": ms_f * 1e3},
+        "kernels_us_min_max": {"pipe_quad_kernel": [t_quad["min"] * 1e3, t_quad["max"] * 1e3],
+                               "pipe_pair_kernel": [t_pair["min"] * 1e3, t_pair["max"] * 1e3],
+                               "pipe_kernel": [t_one["min"] * 1e3, t_one["max"] * 1e3]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes,
+                     "frac_of_measured_copy": achieved / bw["copy_GBs"],
                      "l2_hit_rate": PIPE_COUNTERS["l2_hit_rate"] if traffic is not None else None},
+        "two_frame_step_us": ms_pair * 1e3,
         "two_frame_roofline": {"kernel": "pipe_pair_kernel", "algorithmic_bytes": pair_bytes,
                                "achieved_GBs": pair_bytes / (ms_pair * 1e-3) / 1e9,
                                "frac": pair_bytes / (ms_pair * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "single_frame_pipelined_us": ms * 1e3,
+        "single_frame_path_us": ms_single * 1e3,
         "single_frame_roofline": {"kernel": "pipe_kernel", "algorithmic_bytes": single_bytes,
                                   "achieved_GBs": single_bytes / (ms * 1e-3) / 1e9,
                                   "frac": single_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "quad_bits_equal_single": quad_bits_equal,
+        "pair_bits_equal_single": pair_bits_equal,
+        "one_frame_bits_equal_single": one_bits_equal,
         "parity_max_abs_err": max_err,
+        "c2_sequence": c2,
         "surface": surface,
         "colour": colour,
         "particles": particles,
@@ -394,10 +448,103 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measure_surface(torch, psfs, slot, timed_graph, args):
+def measure_c2(torch, psfs, S, T, bw, args):
+    """The 256^3-voxel, 12-view, 1280x720 workload: its 16-frame sequence (one
+    rig and background model, the body moving 2 cm per frame) as four quad
+    groups through five launches (maps of group 0; maps of group g+1 beside the
+    fusion of group g; fusion of group 3), and the steady-state four-frame
+    step over those groups, plus the one-frame pipelined step."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.time()
+    with ThreadPoolExecutor(8) as ex:
+        frs = list(ex.map(lambda t: S.config_frame(2, t), range(16)))
+    print(f"[bench] generated the 16 frames of the 256^3 sequence in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    fr0 = frs[0]
+    V, npix, n = fr0.grid.nvox, fr0.npix, fr0.n
+    shape = (fr0.grid.nz, fr0.grid.ny, fr0.grid.nx)
+    plan = psfs.Plan(fr0.cams, fr0.grid)
+    plan.set_backgrounds([torch.from_numpy(m).cuda() for m in fr0.mean],
+                         [torch.from_numpy(v).cuda() for v in fr0.var])
+    ims = [[torch.from_numpy(i).cuda() for i in fr.images] for fr in frs]
+    del frs
+    posts = [torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(16)]
+    occs = [torch.empty(shape, dtype=torch.uint8, device="cuda") for _ in range(16)]
+    maps4 = [plan.new_lmap_quad(), plan.new_lmap_quad()]
+    torch.cuda.synchronize()
+
+    def group(g):
+        return ims[4 * g:4 * g + 4], posts[4 * g:4 * g + 4], occs[4 * g:4 * g + 4]
+
+    def seq_launch(i):
+        # launch i of the sequence: maps of group i (i < 4) beside the fusion of group i-1 (i > 0)
+        nxt = group(i)[0] if i < 4 else None
+        cur = group(i - 1) if i > 0 else None
+        plan.pipeline_step_quad(nxt, maps4[i % 2] if nxt else None, maps4[(i - 1) % 2] if cur else None,
+                                cur[1] if cur else None, cur[2] if cur else None)
+
+    t_seq = T.steps(lambda r: [seq_launch(i) for i in range(5)], 1)
+    ms_seq = t_seq["median"]
+
+    def steady(i):
+        c, nx = group(i % 4), group((i + 1) % 4)
+        plan.pipeline_step_quad(nx[0], maps4[(i + 1) % 2], maps4[i % 2], c[1], c[2])
+
+    with torch.cuda.stream(T.stream):
+        steady(3)
+    t_st = T.steps(steady, max(4, min(args.steps, 64)))
+    ms_st = t_st["median"]
+    # bits of the whole sequence against single frames (frames 0 and 15)
+    with torch.cuda.stream(T.stream):
+        for i in range(5):
+            seq_launch(i)
+    torch.cuda.synchronize()
+    bits = True
+    for f in (0, 15):
+        p, _ = plan.reconstruct(ims[f])
+        torch.cuda.synchronize()
+        bits = bits and bool(torch.equal(p, posts[f]))
+        del p
+
+    maps1 = [plan.new_lmap(), plan.new_lmap()]
+
+    def one(i):
+        plan.pipeline_step(ims[(i + 1) % 16], maps1[(i + 1) % 2], maps1[i % 2], posts[i % 16], occs[i % 16])
+
+    with torch.cuda.stream(T.stream):
+        one(15)
+    t_one = T.steps(one, max(16, min(args.steps, 64)))
+    ms_one = t_one["median"]
+    quad_bytes = 36 * npix + 20 * V
+    seq_bytes = 4 * quad_bytes
+    one_bytes = 27 * npix + 5 * V
+    print(f"[bench] 256^3 x 12 sequence of 16 frames: {ms_seq * 1e3:.1f} us ({ms_seq * 1e3 / 16:.2f} us/frame); "
+          f"steady four-frame step {ms_st * 1e3:.1f} us; one-frame step {ms_one * 1e3:.1f} us",
+          file=sys.stderr, flush=True)
+    del ims, posts, occs, maps4, maps1
+    torch.cuda.empty_cache()
+    return {"workload": "256^3 voxel grid over 2.5 m, 8 ring + 4 elevated views 1280x720 f=1000, one background "
+                        "model, 16 frames of the body moving +2 cm/frame",
+            "sequence_us": ms_seq * 1e3, "sequence_us_min_max": [t_seq["min"] * 1e3, t_seq["max"] * 1e3],
+            "launches_per_sequence": 5, "frames_per_s": 16e3 / ms_seq,
+            "voxel_view_per_s": 16 * V * n / (ms_seq * 1e-3),
+            "algorithmic_bytes_per_sequence": seq_bytes,
+            "sequence_frac_of_hbm_peak": seq_bytes / (ms_seq * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "quad_step_us": ms_st * 1e3, "quad_step_us_min_max": [t_st["min"] * 1e3, t_st["max"] * 1e3],
+            "quad_roofline": {"kernel": "pipe_quad_kernel", "algorithmic_bytes_per_launch": quad_bytes,
+                              "achieved_GBs": quad_bytes / (ms_st * 1e-3) / 1e9,
+                              "frac": quad_bytes / (ms_st * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "frac_of_measured_copy": quad_bytes / (ms_st * 1e-3) / 1e9 / bw["copy_GBs"]},
+            "one_frame_step_us": ms_one * 1e3,
+            "one_frame_roofline": {"kernel": "pipe_kernel", "algorithmic_bytes_per_launch": one_bytes,
+                                   "frac": one_bytes / (ms_one * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "bits_equal_single_frames_0_15": bits}
+
+
+def measure_surface(torch, psfs, slot, T, args):
     """Smoothing + threshold + surface list of the headline posterior (three
     launches), replayed from a HIP graph."""
-    plan, post = slot["plan"], slot["post"]
+    plan, post = slot["plan"], slot["posts"][0]
     g = plan.grid
     V = g.nx * g.ny * g.nz
     occ = torch.empty_like(post, dtype=torch.uint8)
@@ -408,7 +555,7 @@ def measure_surface(torch, psfs, slot, timed_graph, args):
     def f():
         plan.surface(post, occ=occ, out=out, count=count, workspace=ws)
 
-    ms = timed_graph([f], max(20, args.steps // 10), 5)
+    ms = T.calls([f])["median"]
     n = int(count.item())
     algo = 4 * V + 1 * V + 4 * n
     print(f"[bench] surface extraction {ms * 1e3:.2f} us ({n} surface voxels)", file=sys.stderr, flush=True)
@@ -428,10 +575,10 @@ def measure_surface(torch, psfs, slot, timed_graph, args):
     return out
 
 
-def measure_colour(torch, psfs, slot, frame, timed_graph, args):
+def measure_colour(torch, psfs, slot, frame, T, args):
     """Colour of the headline frame's surface voxels from its 8 views (four
     launches), replayed from a HIP graph."""
-    plan, post, ims = slot["plan"], slot["post"], slot["ims"]
+    plan, post, ims = slot["plan"], slot["posts"][0], slot["ims"][0]
     idx = plan.surface(post).indices().contiguous()
     n = int(idx.numel())
     colour = torch.empty((n, 3), dtype=torch.float32, device="cuda")
@@ -441,7 +588,7 @@ def measure_colour(torch, psfs, slot, frame, timed_graph, args):
     def f():
         plan.colour(ims, idx, colour=colour, views=views, workspace=ws)
 
-    ms = timed_graph([f], max(20, args.steps // 10), 5)
+    ms = T.calls([f])["median"]
     # algorithmic bytes: the list and its outputs (4 + 12 + 4 B per voxel) and,
     # per (voxel, view), the depth-buffer entry of its pixel cleared, updated
     # and read (3 x 8 B) and the pixel's RGB (3 B)
@@ -459,7 +606,7 @@ def measure_colour(torch, psfs, slot, frame, timed_graph, args):
     return out
 
 
-def measure_particles(torch, psfs, S, timed_graph, args, n_particles=200):
+def measure_particles(torch, psfs, S, T, args, n_particles=200):
     """Particle weights of one annealing layer: 200 particles of the 10-cylinder
     model against the silhouette and edge maps of the 8 views of the 640x480
     workload (weights kernel + normalisation), replayed from a HIP graph."""
@@ -474,7 +621,7 @@ def measure_particles(torch, psfs, S, timed_graph, args, n_particles=200):
     def f():
         plan.particle_weights(cyl, sil, edg, beta=1.0, weights=True, out=out)
 
-    ms = timed_graph([f], max(50, args.steps // 2), 10)
+    ms = T.calls([f])["median"]
     samples = n_particles * len(cams) * 400          # 160 outline + 240 silhouette points per view
     # algorithmic bytes: the cylinders, one FP32 map value per sample point, the outputs
     algo = parts.nbytes + 4 * samples + 16 * n_particles
@@ -496,7 +643,7 @@ def measure_particles(torch, psfs, S, timed_graph, args, n_particles=200):
     return res
 
 
-def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
+def measure_diff(torch, psfs, S, T, args, nslots=4):
     """Differentiable pass on the 128^3 x 8-view workload (bilinear sampling,
     BCE against the ellipsoid occupancy, cameras perturbed 1 %): forward alone
     vs forward + backward, per frame."""
@@ -527,9 +674,9 @@ def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
             d["plan"].diff_backward(d["ims"], d["lab"], d["logits"], d["gl"], d["ws"], None, d["gm"], d["gv"], d["gP"])
         return f
 
-    reps = max(10, args.steps // (4 * nslots))
-    ms_f = timed_graph([fwd(d) for d in slots], reps, 3)
-    ms_fb = timed_graph([fwdbwd(d) for d in slots], reps, 3)
+    t_f = T.calls([fwd(d) for d in slots])
+    t_fb = T.calls([fwdbwd(d) for d in slots])
+    ms_f, ms_fb = t_f["median"], t_fb["median"]
     print(f"[bench] differentiable: fwd {ms_f * 1e3:.2f} us, fwd+bwd {ms_fb * 1e3:.2f} us", file=sys.stderr, flush=True)
     fr = S.config_frame(4, 0)
     npix, V = fr.npix, fr.grid.nvox
@@ -541,6 +688,7 @@ def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
     b_fb = b_f + 51 * npix + 5 * V
     out = {"workload": "128^3 grid, 8 views 640x480, bilinear, BCE loss over the whole grid, cameras perturbed 1 %",
            "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb, "ratio": ms_fb / ms_f, "target_ratio": 3.0,
+           "fwd_ms_min_max": [t_f["min"], t_f["max"]], "fwd_bwd_ms_min_max": [t_fb["min"], t_fb["max"]],
            "roofline": {"bound": "hbm", "fwd_bytes": b_f, "fwd_bwd_bytes": b_fb,
                         "fwd_frac": b_f / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS,
                         "fwd_bwd_frac": b_fb / (ms_fb * 1e-3) / 1e9 / HBM_PEAK_GBS}}
@@ -548,14 +696,13 @@ def measure_diff(torch, psfs, S, timed_graph, args, nslots=4):
         from oracle import oracle as O
         cams = S.perturb_cameras(fr.cams, seed=(4, 0))
         lab = S.gt_occupancy(fr.grid, fr.body)
-        t0 = time.time()
-        nrep = 0
-        while nrep < 1 or (time.time() - t0 < args.cpu_seconds / 2 and nrep < 20):
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
             O.grad(cams, fr.grid, fr.images, fr.mean, fr.var, lab)    # forward + loss + adjoint
-            nrep += 1
-        dt = time.time() - t0
-        out["cpu_oracle"] = {"ms_fwd_bwd": 1e3 * dt / nrep, "cores": O.threads(), "kind": "oracle",
-                             "sample": f"{nrep} full fwd+bwd frames (FP64 C oracle), {dt:.1f} s"}
+            ts.append(time.perf_counter() - t0)
+        out["cpu_oracle"] = {"ms_fwd_bwd": 1e3 * float(np.median(ts)), "cores": O.threads(), "kind": "oracle",
+                             "sample": "median of 5 full fwd+bwd frames (FP64 C oracle, all threads)"}
     return out
 
 
@@ -580,19 +727,20 @@ def measure_batch(torch, psfs, S, args, nframes=64):
     tile = b.tune()
     b.run()
     torch.cuda.synchronize()
-    reps = 10
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+    ts = []
+    for _ in range(args.replays):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         b.run()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
     algo = 27 * px + 5 * vox
     print(f"[bench] batch of {nframes}: {ms:.3f} ms per run (tile {tile}, generated in {gen_s:.0f}s)",
           file=sys.stderr, flush=True)
     return {"workload": f"{nframes} uneven frames (grid edge 64..192, 4..12 views, 320x240..1280x720)",
-            "ms_per_run": ms, "frames_per_s": nframes / (ms * 1e-3), "voxel_view_per_s": vv / (ms * 1e-3),
+            "ms_per_run": ms, "ms_per_run_min_max": [min(ts), max(ts)], "frames_per_s": nframes / (ms * 1e-3), "voxel_view_per_s": vv / (ms * 1e-3),
             "algorithmic_bytes": algo, "achieved_GBs": algo / (ms * 1e-3) / 1e9,
             "frac_of_hbm_peak": algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tile": psfs.tiles()[tile]}
 

@@ -65,7 +65,9 @@ enum psfs_status {
     PSFS_E_WORKSPACE = -4,  /* workspace missing or smaller than required */
     PSFS_E_HIP = -5,        /* HIP runtime error; text in psfs_last_error() */
     PSFS_E_DEVICE = -6,     /* the current device is not a gfx950 GPU */
-    PSFS_E_STALE = -7       /* batch update changes the captured shapes */
+    PSFS_E_STALE = -7,      /* batch update changes the captured shapes */
+    PSFS_E_INPUT = -8       /* invalid input values found by the optional device
+                               check (psfs_set_input_check / psfs_input_status) */
 };
 
 enum psfs_sampling {
@@ -121,9 +123,26 @@ int psfs_set_cameras(psfs_plan *plan, int n, const psfs_camera *cams);
 int psfs_set_grid(psfs_plan *plan, const psfs_grid *grid);
 int psfs_set_params(psfs_plan *plan, const psfs_params *params);
 /* Background model of view `view` (Eq. 1): borrowed device pointers to FP32
- * [H][W][3] means and variances (variances > 0 and finite; the kernels do not
- * re-check). The caller keeps them alive while work that reads them runs. */
+ * [H][W][3] means and variances (variances > 0 and finite, means finite;
+ * checked on the device only when the input check below is on). The caller
+ * keeps them alive while work that reads them runs. */
 int psfs_set_background(psfs_plan *plan, int view, const float *mean_dev, const float *var_dev);
+
+/* Optional device check of the background model (Eq. 1 is defined only for
+ * positive finite variances). flags_dev: a caller-owned, 4-byte aligned device
+ * word, zero before the first checked call (NULL turns the check off, the
+ * default). While it is set, every likelihood pass of this plan
+ * (psfs_likelihood, psfs_reconstruct, the pipelined steps, psfs_diff_forward)
+ * also tests each mean (finite) and variance (positive and finite) it reads
+ * and sets bit k of *flags_dev when view k holds an invalid value; the maps
+ * and posteriors it writes are then meaningless (NaN or infinite values), but
+ * no kernel faults. Batches are not checked. */
+int psfs_set_input_check(psfs_plan *plan, uint32_t *flags_dev);
+/* After the caller has synchronised with the checked work: reads the flags
+ * (a blocking 4-byte copy). Returns PSFS_OK if no invalid value was seen, else
+ * clears the word and returns PSFS_E_INPUT with the views named in
+ * psfs_last_error(); PSFS_E_NOT_READY if no flags are set. */
+int psfs_input_status(psfs_plan *plan);
 
 /* Likelihood-map layout: view k occupies floats [offset(k), offset(k) + W_k*H_k)
  * of one buffer, offsets padded to multiples of 64 floats. Returns the total

@@ -47,6 +47,8 @@ def lib():
                            C.POINTER(C.c_uint8), C.POINTER(C.c_float))
         dpp = C.POINTER(dp)
         L.psfs_oracle_threads.restype = C.c_int
+        L.psfs_oracle_set_threads.argtypes = [C.c_int]
+        L.psfs_oracle_set_threads.restype = None
         L.psfs_oracle_slm.argtypes = [C.c_int64, u8p, fp, fp, C.c_double, dp]
         L.psfs_oracle_log2slm.argtypes = [C.c_int64, u8p, fp, fp, C.c_double, dp]
         L.psfs_oracle_fuse_views.argtypes = [C.c_int, dp, C.c_double]
@@ -66,6 +68,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().psfs_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the later oracle calls (for timing)."""
+    lib().psfs_oracle_set_threads(int(n))
 
 
 # ----------------------------------------------------------------- marshalling

@@ -54,6 +54,17 @@ int psfs_oracle_threads(void)
 #endif
 }
 
+/* Thread count of the later parallel loops (timing at 1 thread and at all
+ * host cores); n <= 0 leaves it unchanged. */
+void psfs_oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Eq. 1-2: silhouette likelihood map                                       */
 /* ------------------------------------------------------------------------ */

@@ -18,7 +18,7 @@ NEAREST, BILINEAR = 0, 1
 
 STATUS = {
     0: "PSFS_OK", -1: "PSFS_E_ARG", -2: "PSFS_E_RANGE", -3: "PSFS_E_NOT_READY",
-    -4: "PSFS_E_WORKSPACE", -5: "PSFS_E_HIP", -6: "PSFS_E_DEVICE", -7: "PSFS_E_STALE",
+    -4: "PSFS_E_WORKSPACE", -5: "PSFS_E_HIP", -6: "PSFS_E_DEVICE", -7: "PSFS_E_STALE", -8: "PSFS_E_INPUT",
 }
 
 
@@ -65,6 +65,8 @@ SIGNATURES = {
     "psfs_set_grid": (C.c_int, [vp, C.POINTER(psfs_grid)]),
     "psfs_set_params": (C.c_int, [vp, C.POINTER(psfs_params)]),
     "psfs_set_background": (C.c_int, [vp, C.c_int, vp, vp]),
+    "psfs_set_input_check": (C.c_int, [vp, vp]),
+    "psfs_input_status": (C.c_int, [vp]),
     "psfs_lmap_floats": (C.c_int64, [vp]),
     "psfs_lmap_offset": (C.c_int64, [vp, C.c_int]),
     "psfs_workspace_bytes": (C.c_size_t, [vp]),

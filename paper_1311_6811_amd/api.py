@@ -125,6 +125,21 @@ class Plan:
             self.set_background(k, m, v)
 
     # --------------------------------------------------------- buffers
+    def set_input_check(self, flags: Optional[torch.Tensor]) -> None:
+        """Device check of the background model (variances positive and
+        finite, means finite) in every later likelihood pass of this plan:
+        `flags` is a zeroed one-element int32 GPU tensor that receives bit k
+        when view k holds an invalid value; None turns the check off."""
+        ptr = _dev(flags, torch.int32, "flags", (1,)) if flags is not None else None
+        L.check(L.lib().psfs_set_input_check(self._h, ptr))
+        self._check_flags = flags                  # keep the word alive while the plan uses it
+
+    def input_status(self) -> None:
+        """After synchronising with the checked work: raises PsfsError
+        (PSFS_E_INPUT, naming the views) if an invalid value was seen, and
+        clears the flags."""
+        L.check(L.lib().psfs_input_status(self._h))
+
     @property
     def n(self) -> int:
         return len(self.cams)
@@ -149,6 +164,16 @@ class Plan:
                 for k, (im, c) in enumerate(zip(images, self.cams))]
         return L.ptr_array(ptrs)
 
+    def _map(self, t: torch.Tensor, frames: int, name: str) -> int:
+        """Device pointer of a map buffer that must hold `frames` interleaved
+        frames' maps (frames * lmap_floats() FP32 values): the C entry points
+        take no length for it, so a short buffer is refused here."""
+        need = frames * self.lmap_floats()
+        if t is None or t.numel() < need:
+            got = None if t is None else t.numel()
+            raise ValueError(f"{name}: needs at least {need} float32 elements ({frames} x lmap_floats), got {got}")
+        return _dev(t, torch.float32, name)
+
     def lmap_view(self, lmap: torch.Tensor, view: int) -> torch.Tensor:
         c = self.cams[view]
         off = self.lmap_offset(view)
@@ -158,7 +183,7 @@ class Plan:
     def likelihood(self, images: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Eq. 1-2: log(2*SLM) maps of all views in one buffer (psfs_lmap_* layout)."""
         lmap = out if out is not None else torch.empty(max(self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
-        L.check(L.lib().psfs_likelihood(self._h, self._images(images), _dev(lmap, torch.float32, "lmap"), _stream()))
+        L.check(L.lib().psfs_likelihood(self._h, self._images(images), self._map(lmap, 1, "lmap"), _stream()))
         return lmap
 
     def _outputs(self, posterior, occ, want_occ):
@@ -174,7 +199,7 @@ class Plan:
     def fuse(self, lmap: torch.Tensor, posterior=None, occ=None, want_occ=True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
         """Eq. 3-9 (+ threshold) from likelihood maps."""
         post, occ, pp, op = self._outputs(posterior, occ, want_occ)
-        L.check(L.lib().psfs_fuse(self._h, _dev(lmap, torch.float32, "lmap"), pp, op, _stream()))
+        L.check(L.lib().psfs_fuse(self._h, self._map(lmap, 1, "lmap"), pp, op, _stream()))
         return post, occ
 
     def reconstruct(self, images: Sequence[torch.Tensor], posterior=None, occ=None, workspace=None,
@@ -196,13 +221,13 @@ class Plan:
         the maps `lmap_cur` (from an earlier step) into `posterior` / `occ`.
         Either part may be omitted (images=None / posterior=None)."""
         ims = self._images(images) if images is not None else None
-        nxt = _dev(lmap_next, torch.float32, "lmap_next") if images is not None else None
+        nxt = self._map(lmap_next, 1, "lmap_next") if images is not None else None
         cur = pp = op = None
         if posterior is not None:
             shape = (self.grid.nz, self.grid.ny, self.grid.nx)
             pp = _dev(posterior, torch.float32, "posterior", shape)
             op = _dev(occ, torch.uint8, "occ", shape) if occ is not None else None
-            cur = _dev(lmap_cur, torch.float32, "lmap_cur")
+            cur = self._map(lmap_cur, 1, "lmap_cur")
         L.check(L.lib().psfs_pipeline_step(self._h, ims, nxt, cur, pp, op, _stream()))
 
     def new_lmap_pair(self) -> torch.Tensor:
@@ -217,13 +242,13 @@ class Plan:
         (post_a, occ_a) and (post_b, occ_b). Either part may be omitted."""
         ia = self._images(images_a) if images_a is not None else None
         ib = self._images(images_b) if images_b is not None else None
-        nxt = _dev(lmap2_next, torch.float32, "lmap2_next") if images_a is not None else None
+        nxt = self._map(lmap2_next, 2, "lmap2_next") if images_a is not None else None
         shape = (self.grid.nz, self.grid.ny, self.grid.nx)
         pa = _dev(post_a, torch.float32, "post_a", shape) if post_a is not None else None
         pb = _dev(post_b, torch.float32, "post_b", shape) if post_b is not None else None
         oa = _dev(occ_a, torch.uint8, "occ_a", shape) if occ_a is not None else None
         ob = _dev(occ_b, torch.uint8, "occ_b", shape) if occ_b is not None else None
-        cur = _dev(lmap2_cur, torch.float32, "lmap2_cur") if (post_a is not None or post_b is not None) else None
+        cur = self._map(lmap2_cur, 2, "lmap2_cur") if (post_a is not None or post_b is not None) else None
         L.check(L.lib().psfs_pipeline_step_pair(self._h, ia, ib, nxt, cur, pa, oa, pb, ob, _stream()))
 
     def new_lmap_quad(self) -> torch.Tensor:
@@ -244,7 +269,7 @@ class Plan:
                 raise ValueError(f"expected the images of 4 frames, got {len(images)}")
             flat = [p for fr in images for p in self._images(fr)[:self.n]]
             ims = L.ptr_array(flat)
-            nxt = _dev(lmap4_next, torch.float32, "lmap4_next")
+            nxt = self._map(lmap4_next, 4, "lmap4_next")
         pp = op = cur = None
         if posts is not None:
             if len(posts) != 4 or (occs is not None and len(occs) != 4):
@@ -254,7 +279,7 @@ class Plan:
             if occs is not None:
                 op = L.ptr_array([_dev(t, torch.uint8, f"occs[{f}]", shape) if t is not None else None
                                   for f, t in enumerate(occs)])
-            cur = _dev(lmap4_cur, torch.float32, "lmap4_cur")
+            cur = self._map(lmap4_cur, 4, "lmap4_cur")
         L.check(L.lib().psfs_pipeline_step_quad(self._h, ims, nxt, cur, pp, op, _stream()))
 
     # ------------------------------------- smoothing and surface voxels
@@ -334,7 +359,7 @@ class Plan:
                               for k, (m, c) in enumerate(zip(masks, self.cams))])
         out = out if out is not None else torch.empty(L.FG_BINS, dtype=torch.float32, device="cuda")
         ws = workspace if workspace is not None else torch.empty(4 * L.FG_BINS, dtype=torch.uint8, device="cuda")
-        L.check(L.lib().psfs_foreground_model(self._h, ims, mp, _dev(lmap, torch.float32, "lmap") if lmap is not None else None,
+        L.check(L.lib().psfs_foreground_model(self._h, ims, mp, self._map(lmap, 1, "lmap") if lmap is not None else None,
                                               _dev(out, torch.float32, "log_density", (L.FG_BINS,)),
                                               _dev(ws, torch.uint8, "workspace"), ws.numel(), _stream()))
         return out

@@ -21,6 +21,7 @@ struct psfs_plan {
     const float *mean[PSFS_MAX_VIEWS] = {};
     const float *var[PSFS_MAX_VIEWS] = {};
     const float *fg = nullptr;                      // learned foreground model (log density per bin)
+    uint32_t *check = nullptr;                      // input-check flags (caller's device word), or off
     int tile = -1;
 };
 
@@ -153,6 +154,7 @@ int64_t fill_slm(const psfs_plan *p, const uint8_t *const *images, float *lmap, 
     a.n = p->n;
     a.lmap = lmap;
     a.fg = use_fg ? p->fg : nullptr;
+    a.check = p->check;
     a.k0 = a.fg ? static_cast<float>(-1.5 * std::log(2.0 * M_PI))
                 : static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(p->params.log_u));
     int64_t max_np = 0;
@@ -308,6 +310,7 @@ const char *psfs_status_str(int status)
     case PSFS_E_HIP: return "HIP runtime error";
     case PSFS_E_DEVICE: return "unsupported device";
     case PSFS_E_STALE: return "batch shape changed";
+    case PSFS_E_INPUT: return "invalid input values";
     default: return "unknown status";
     }
 }
@@ -388,6 +391,34 @@ int psfs_set_background(psfs_plan *plan, int view, const float *mean_dev, const 
     plan->mean[view] = mean_dev;
     plan->var[view] = var_dev;
     return PSFS_OK;
+}
+
+int psfs_set_input_check(psfs_plan *plan, uint32_t *flags_dev)
+{
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (flags_dev && !aligned(flags_dev, 4)) return fail(PSFS_E_ARG, "flags must be a 4-byte aligned device pointer");
+    plan->check = flags_dev;
+    return PSFS_OK;
+}
+
+int psfs_input_status(psfs_plan *plan)
+{
+    PSFS_GUARD_BEGIN
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    if (!plan->check) return fail(PSFS_E_NOT_READY, "no input-check flags set (psfs_set_input_check)");
+    uint32_t flags = 0;
+    hipError_t e = hipMemcpy(&flags, plan->check, sizeof(flags), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the input-check flags");
+    if (flags == 0) return PSFS_OK;
+    const uint32_t zero = 0;
+    e = hipMemcpy(plan->check, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing the input-check flags");
+    std::string views;
+    for (int k = 0; k < 32; ++k)
+        if (flags & (1u << k)) views += (views.empty() ? "" : ", ") + std::to_string(k);
+    return fail(PSFS_E_INPUT, "background model of view(s) %s holds a variance <= 0, NaN or Inf or a non-finite mean",
+                views.c_str());
+    PSFS_GUARD_END
 }
 
 int64_t psfs_lmap_floats(const psfs_plan *plan)

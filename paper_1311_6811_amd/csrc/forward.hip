@@ -26,9 +26,9 @@ __global__ __launch_bounds__(256) void slm_kernel(SlmArgs a)
     const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * kWavePixels;
     float *out = a.lmap + sv.map_off;
     if (p0 + kWavePixels <= sv.npix)
-        slm_wave(sv.img, sv.mean, sv.var, out, p0, a.k0, stage[wave], a.fg);
+        slm_wave(sv.img, sv.mean, sv.var, out, p0, a.k0, stage[wave], a.fg, InputCheck{a.check, 1u << blockIdx.y});
     else if (p0 < sv.npix)
-        slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, a.k0, a.fg);
+        slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, a.k0, a.fg, InputCheck{a.check, 1u << blockIdx.y});
 }
 
 // Lane layout: a workgroup covers a TX x TY tile of voxel columns (x fastest,
@@ -90,9 +90,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_kernel(SlmArgs s, FuseArgs f, Pi
         const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * 4 + wave) * kWavePixels;
         float *out = s.lmap + sv.map_off;
         if (p0 + kWavePixels <= sv.npix)
-            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave], s.fg);
+            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave], s.fg, InputCheck{s.check, 1u << v});
         else if (p0 < sv.npix)
-            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0, s.fg);
+            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0, s.fg, InputCheck{s.check, 1u << v});
     } else {
         const int fr = round - p.slm_rounds;
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + fr;
@@ -121,9 +121,11 @@ __global__ __launch_bounds__(TX * TY) void pipe_pair_kernel(SlmArgs s, PairImage
         const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * 4 + wave) * kWavePixels;
         float *out2 = s.lmap + 2 * sv.map_off;
         if (p0 + kWavePixels <= sv.npix)
-            slm_wave_pair(sv.img, ib.img[v], sv.mean, sv.var, out2, p0, s.k0, stage[wave], s.fg);
+            slm_wave_pair(sv.img, ib.img[v], sv.mean, sv.var, out2, p0, s.k0, stage[wave], s.fg,
+                          InputCheck{s.check, 1u << v});
         else if (p0 < sv.npix)
-            slm_wave_pair_tail(sv.img, ib.img[v], sv.mean, sv.var, out2, p0, sv.npix, s.k0, s.fg);
+            slm_wave_pair_tail(sv.img, ib.img[v], sv.mean, sv.var, out2, p0, sv.npix, s.k0, s.fg,
+                               InputCheck{s.check, 1u << v});
     } else {
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
         if (tile >= p.fuse_tiles) return;
@@ -165,9 +167,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImage
         float *out4 = s.lmap + 4 * sv.map_off;
         const uint8_t *const img[4] = {sv.img, qi.img[0][v], qi.img[1][v], qi.img[2][v]};
         if (p0 + kWavePixels <= sv.npix)
-            slm_wave_quad(img, sv.mean, sv.var, out4, p0, s.k0, stage[wave], s.fg);
+            slm_wave_quad(img, sv.mean, sv.var, out4, p0, s.k0, stage[wave], s.fg, InputCheck{s.check, 1u << v});
         else if (p0 < sv.npix)
-            slm_wave_quad_tail(img, sv.mean, sv.var, out4, p0, sv.npix, s.k0, s.fg);
+            slm_wave_quad_tail(img, sv.mean, sv.var, out4, p0, sv.npix, s.k0, s.fg, InputCheck{s.check, 1u << v});
     } else {
         const int64_t tile = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
         if (tile >= p.fuse_tiles) return;

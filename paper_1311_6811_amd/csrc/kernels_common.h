@@ -112,6 +112,34 @@ __device__ __forceinline__ f32x4 quad_k0(const Quad &q, float k0, const float *f
 
 constexpr int kWavePixels = 256;        // pixels per wave in the likelihood kernels
 
+// Optional input validation: Eq. 1 needs every background variance positive
+// and finite and every mean finite. A value class test (one instruction per
+// value) flags NaN, infinities, zeros and negative variances.
+constexpr int kClassPosFinite = (1 << 7) | (1 << 8);            // +denormal, +normal
+constexpr int kClassFinite = 0x1f8;                             // -normal .. +normal
+
+__device__ __forceinline__ bool mean_invalid(float m) { return !__builtin_amdgcn_classf(m, kClassFinite); }
+__device__ __forceinline__ bool var_invalid(float v) { return !__builtin_amdgcn_classf(v, kClassPosFinite); }
+
+__device__ __forceinline__ bool vec_invalid(const f32x4 &m, const f32x4 &v)
+{
+    return mean_invalid(m.x) | mean_invalid(m.y) | mean_invalid(m.z) | mean_invalid(m.w) | var_invalid(v.x) |
+           var_invalid(v.y) | var_invalid(v.z) | var_invalid(v.w);
+}
+
+// Where a wave reports an invalid background value: bit `bit` of *flags
+// (view k -> bit k); flags == nullptr turns the check off.
+struct InputCheck {
+    uint32_t *flags;
+    uint32_t bit;
+};
+
+// Called by all 64 lanes of a wave: one atomic OR when any lane saw a bad value.
+__device__ __forceinline__ void report_wave(const InputCheck &chk, bool bad)
+{
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(chk.flags, chk.bit);
+}
+
 // LDS of one wave in slm_wave: 192 16-byte vectors (means, then variances)
 // and 192 image words.
 struct SlmStage {
@@ -128,6 +156,16 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The check for the pixels [p, min(p + 4, npix)) of a lane in a wave's tail
+// (lanes may have no pixels; each lane with a bad value reports itself).
+__device__ __forceinline__ void tail_check(const float *mean, const float *var, int64_t p, int64_t npix,
+                                           const InputCheck &chk)
+{
+    bool bad = false;
+    for (int64_t t = 3 * p; t < 3 * p + 12 && t < 3 * npix; ++t) bad |= mean_invalid(mean[t]) | var_invalid(var[t]);
+    if (bad) atomicOr(chk.flags, chk.bit);
+}
+
 // log(2*SLM) of the kWavePixels pixels [p0, p0 + 256) of one view, all inside
 // the view, p0 a multiple of 4. Each global load instruction of the wave reads
 // one contiguous span (64 x 16 B of means or variances, 64 x 4 B of image
@@ -136,7 +174,8 @@ __device__ __forceinline__ void wave_lds_sync()
 // per-quad load (48 B apart per lane) touches three times the cache lines per
 // instruction and measured ~40 % slower.
 __device__ __forceinline__ void slm_wave(const uint8_t *img, const float *mean, const float *var, float *out,
-                                         int64_t p0, float k0, SlmStage &st, const float *fg)
+                                         int64_t p0, float k0, SlmStage &st, const float *fg,
+                                         InputCheck chk = InputCheck{nullptr, 0})
 {
     const int lane = static_cast<int>(threadIdx.x & 63);
     const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
@@ -150,6 +189,7 @@ __device__ __forceinline__ void slm_wave(const uint8_t *img, const float *mean, 
         v[r] = __builtin_nontemporal_load(vp + lane + 64 * r);
         w[r] = __builtin_nontemporal_load(ip + lane + 64 * r);
     }
+    if (chk.flags) report_wave(chk, vec_invalid(m[0], v[0]) | vec_invalid(m[1], v[1]) | vec_invalid(m[2], v[2]));
     Quad q;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -175,9 +215,11 @@ __device__ __forceinline__ void slm_wave(const uint8_t *img, const float *mean, 
 // The same for a wave whose span [p0, p0 + 256) reaches past npix: lane l
 // converts its quad p0 + 4l directly, or the pixels of it below npix.
 __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *mean, const float *var, float *out,
-                                              int64_t p0, int64_t npix, float k0, const float *fg)
+                                              int64_t p0, int64_t npix, float k0, const float *fg,
+                                              InputCheck chk = InputCheck{nullptr, 0})
 {
     const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    if (chk.flags) tail_check(mean, var, p, npix, chk);
     if (p + 4 <= npix) {
         Quad q;
         const uint32_t *iw = reinterpret_cast<const uint32_t *>(img + 3 * p);
@@ -212,7 +254,7 @@ __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *m
 // writes pixels p0 + 4l .. p0 + 4l + 3 of both frames with two 16-byte stores.
 __device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_t *img_b, const float *mean,
                                               const float *var, float *out2, int64_t p0, float k0, SlmStage &st,
-                                              const float *fg)
+                                              const float *fg, InputCheck chk)
 {
     const int lane = static_cast<int>(threadIdx.x & 63);
     const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
@@ -228,6 +270,7 @@ __device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_
         wa[r] = __builtin_nontemporal_load(ia + lane + 64 * r);
         wb[r] = __builtin_nontemporal_load(ib + lane + 64 * r);
     }
+    if (chk.flags) report_wave(chk, vec_invalid(m[0], v[0]) | vec_invalid(m[1], v[1]) | vec_invalid(m[2], v[2]));
     Quad qa, qb;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -268,9 +311,10 @@ __device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_
 // slm_wave_tail for two frames.
 __device__ __forceinline__ void slm_wave_pair_tail(const uint8_t *img_a, const uint8_t *img_b, const float *mean,
                                                    const float *var, float *out2, int64_t p0, int64_t npix, float k0,
-                                                   const float *fg)
+                                                   const float *fg, InputCheck chk)
 {
     const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    if (chk.flags) tail_check(mean, var, p, npix, chk);
     for (int64_t t = p; t < p + 4 && t < npix; ++t) {
         const uint8_t *A = img_a + 3 * t, *B = img_b + 3 * t;
         const float *mm = mean + 3 * t, *vv = var + 3 * t;
@@ -291,7 +335,8 @@ __device__ __forceinline__ void slm_wave_pair_tail(const uint8_t *img_a, const u
 // through the same LDS words. Lane l writes pixels p0 + 4l .. p0 + 4l + 3 of
 // the four frames with four 16-byte stores.
 __device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], const float *mean, const float *var,
-                                              float *out4, int64_t p0, float k0, SlmStage &st, const float *fg)
+                                              float *out4, int64_t p0, float k0, SlmStage &st, const float *fg,
+                                              InputCheck chk)
 {
     const int lane = static_cast<int>(threadIdx.x & 63);
     const f32x4 *mp = reinterpret_cast<const f32x4 *>(mean + 3 * p0);
@@ -309,6 +354,7 @@ __device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], co
 #pragma unroll
         for (int r = 0; r < 3; ++r) w[f][r] = __builtin_nontemporal_load(ip + lane + 64 * r);
     }
+    if (chk.flags) report_wave(chk, vec_invalid(m[0], v[0]) | vec_invalid(m[1], v[1]) | vec_invalid(m[2], v[2]));
     Quad q;
     uint32_t qw[4][3];
 #pragma unroll
@@ -361,9 +407,10 @@ __device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], co
 // slm_wave_tail for four frames.
 __device__ __forceinline__ void slm_wave_quad_tail(const uint8_t *const (&img)[4], const float *mean,
                                                    const float *var, float *out4, int64_t p0, int64_t npix, float k0,
-                                                   const float *fg)
+                                                   const float *fg, InputCheck chk)
 {
     const int64_t p = p0 + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    if (chk.flags) tail_check(mean, var, p, npix, chk);
     for (int64_t t = p; t < p + 4 && t < npix; ++t) {
         const float *mm = mean + 3 * t, *vv = var + 3 * t;
 #pragma unroll

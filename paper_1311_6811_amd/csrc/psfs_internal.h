@@ -27,6 +27,7 @@ struct SlmArgs {
     SlmView view[kMaxViews];
     float *lmap;
     const float *fg;                    // nullable: log density per colour bin of a learned foreground model
+    uint32_t *check;                    // nullable: bit k set when view k's background holds an invalid value
     float k0;                           // -1.5*log(2*pi) - log_u; -1.5*log(2*pi) with fg
     int32_t n;
 };

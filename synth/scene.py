@@ -61,8 +61,8 @@ BODY_PARTS = (
 )
 
 
-def rng_for(config: int, frame: int, stream: int) -> np.random.Generator:
-    return np.random.default_rng([int(config), int(frame), int(stream)])
+def rng_for(config: int, frame: int, stream: int, *more: int) -> np.random.Generator:
+    return np.random.default_rng([int(config), int(frame), int(stream)] + [int(m) for m in more])
 
 
 @dataclass
@@ -264,12 +264,15 @@ def render_image(mask: np.ndarray, mean: np.ndarray, var: np.ndarray,
 
 
 def render_frame(config: int, frame: int, cams: List[Camera], grid: Grid,
-                 body: List[Ellipsoid], bg_key: Tuple[int, int]) -> Frame:
+                 body: List[Ellipsoid], bg_key: Tuple[int, int], seq: Tuple[int, ...] = ()) -> Frame:
+    """Images of `body` seen by `cams` against the background model of
+    `bg_key`; image noise is seeded by (config, frame) and, for the later
+    frames of a sequence, by `seq` as well."""
     images, means, vars_, masks = [], [], [], []
     rbg = rng_for(bg_key[0], bg_key[1], STREAM_BG)
-    rn = rng_for(config, frame, STREAM_NOISE)
-    rf = rng_for(config, frame, STREAM_FG)
-    ro = rng_for(config, frame, STREAM_OUTLIER)
+    rn = rng_for(config, frame, STREAM_NOISE, *seq)
+    rf = rng_for(config, frame, STREAM_FG, *seq)
+    ro = rng_for(config, frame, STREAM_OUTLIER, *seq)
     for cam in cams:
         m, v = make_background(rbg, cam.height, cam.width)
         mask = render_mask(cam, body)
@@ -331,6 +334,37 @@ def config_frame(config: int, frame: int = 0) -> Frame:
     fr = render_frame(src_cfg, frame, cams, grid, body, bg_key)
     fr.config = config
     return fr
+
+
+def sequence_frame(config: int, slot: int, t: int) -> Frame:
+    """Frame t of the frame sequence that starts with config_frame(config, slot):
+    the same rig, grid and background model, the slot's body moved rigidly by
+    +2 cm along x per frame, and fresh image noise (t = 0 is that frame).
+    The 256^3 workload is already one sequence (config_frame(2, t))."""
+    if config == 2:
+        return config_frame(2, slot + t)
+    if config not in (0, 1):
+        raise ValueError(f"no frame sequence for config {config}")
+    if t == 0:
+        return config_frame(config, slot)
+    fr0 = config_frame_rig(config)
+    body = make_body(rng_for(config, slot, STREAM_BODY), shift=(0.02 * t, 0.0, 0.0))
+    fr = render_frame(config, slot, fr0[0], fr0[1], body, (config, slot), seq=(t,))
+    return fr
+
+
+def config_frame_rig(config: int):
+    """(cameras, grid) of a named workload with one rig (configs 0, 1, 2, 4)."""
+    if config == 0:
+        f, W, H = IMAGE_CLASSES[0]
+        return ring_rig(4, f, W, H), cube_grid(64, 2.0)
+    if config in (1, 4):
+        f, W, H = IMAGE_CLASSES[1]
+        return ring_rig(8, f, W, H), cube_grid(128, 2.0)
+    if config == 2:
+        f, W, H = IMAGE_CLASSES[2]
+        return ring_plus_elevated_rig(f, W, H), cube_grid(256, 2.5)
+    raise ValueError(f"config {config} has no single rig")
 
 
 def perturb_cameras(cams: Sequence[Camera], seed=(4, 0), rel: float = 0.01) -> List[Camera]:

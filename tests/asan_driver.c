@@ -50,6 +50,10 @@ int main(void)
     CALL(psfs_set_background(p, 0, NULL, (const float *)fk));
     CALL(psfs_set_background(p, 0, (const float *)((char *)fk + 4), (const float *)fk));
     for (int k = 0; k < 16; ++k) CALL(psfs_set_background(p, k, (const float *)fk, (const float *)fk));
+    CALL(psfs_set_input_check(NULL, NULL));
+    CALL(psfs_set_input_check(p, (uint32_t *)((char *)fk + 2)));
+    CALL(psfs_input_status(NULL));
+    CALL(psfs_input_status(p));
     for (int k = -1; k <= 16; ++k) CALL(psfs_lmap_offset(p, k));
     CALL(psfs_lmap_floats(p)); CALL(psfs_workspace_bytes(p)); CALL(psfs_diff_workspace_bytes(p));
     CALL(psfs_surface_workspace_bytes(p)); CALL(psfs_colour_workspace_bytes(p));

@@ -62,8 +62,8 @@ def _cam(W=8, H=6):
 
 
 def test_status_strings(lib):
-    for s in range(-7, 1):
-        assert lib.psfs_status_str(s)
+    for s in range(-8, 1):
+        assert lib.psfs_status_str(s) and lib.psfs_status_str(s) != b"unknown status"
     assert lib.psfs_version() == 1
 
 
@@ -422,3 +422,34 @@ def test_batch_validation_without_device(lib):
     assert lib.psfs_batch_set_tile(None, 0) == -1
     assert lib.psfs_batch_run(None, None, 0, None) == -1
     lib.psfs_batch_destroy(None)
+
+
+def test_short_map_buffers_are_refused_before_any_launch(lib):
+    """The map arguments of the C entry points carry no length, so the binding
+    checks that a buffer holds k x lmap_floats values (k frames interleaved)
+    before it passes the pointer on."""
+    import torch
+    from synth import scene as S
+    cams, grid = S.config_frame_rig(0)
+    plan = psfs.Plan(cams, grid)
+    nf = plan.lmap_floats()
+    assert nf == sum(c.width * c.height for c in cams)        # 64-float aligned views of 320x240
+    for frames in (1, 2, 4):
+        with pytest.raises(ValueError, match=f"{frames} x lmap_floats"):
+            plan._map(torch.empty(frames * nf - 1, dtype=torch.float32), frames, "lmap")
+        with pytest.raises(ValueError):
+            plan._map(None, frames, "lmap")
+    with pytest.raises(TypeError, match="GPU tensor"):              # long enough: the device check follows
+        plan._map(torch.empty(4 * nf, dtype=torch.float32), 4, "lmap")
+
+
+def test_input_check_validation_without_device(lib):
+    assert lib.psfs_set_input_check(None, None) == -1
+    h = _plan(lib)
+    assert lib.psfs_input_status(h) == -3                              # no flags word set
+    assert lib.psfs_set_input_check(h, C.c_void_p(0x100002)) == -1     # misaligned
+    assert lib.psfs_set_input_check(h, C.c_void_p(0x100004)) == 0
+    assert lib.psfs_set_input_check(h, None) == 0                      # off again
+    assert lib.psfs_input_status(h) == -3
+    assert lib.psfs_input_status(None) == -1
+    lib.psfs_plan_destroy(h)

@@ -144,3 +144,30 @@ def test_quad_largest_workload():
     plan, images = sequence(frames)
     outs = run_quads(plan, images)
     assert_frames_match(plan, images, outs)
+
+
+def test_quad_whole_256cube_sequence_and_oracle():
+    """The whole 16-frame sequence of the 256^3-voxel, 12-view, 1280x720
+    workload (one rig and background model, the body moving 2 cm per frame)
+    as four quad groups through five launches: every frame bit-identical to
+    that frame reconstructed alone, and the last frame against the FP64
+    oracle (unambiguous voxels within 1e-5, ambiguous ones within their
+    admissible range, decided occupancy exact)."""
+    from concurrent.futures import ThreadPoolExecutor
+    say("four-frame steps, whole 16-frame sequence at 256^3 x 12 views of 1280x720")
+    with ThreadPoolExecutor(8) as ex:
+        frames = list(ex.map(lambda t: S.config_frame(2, t), range(16)))
+    last = frames[15]
+    for fr in frames[1:15]:
+        fr.mean, fr.var = None, None                  # one background model for the rig: frame 0's
+    ims0, mus, vs = upload(frames[0])
+    plan = plan_for(frames[0], mus, vs)
+    images = [ims0] + [[torch.from_numpy(i).cuda() for i in fr.images] for fr in frames[1:]]
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+    say("  frames bit-identical; oracle on frame 15")
+    maps = [O.slm(i, m, v) for i, m, v in zip(last.images, last.mean, last.var)]
+    ref = O.posterior(last.cams, last.grid, maps)
+    assert_posterior_parity(outs[15][0], ref, combos=lambda v: O.voxel_combos(last.cams, last.grid, maps, v),
+                            n_enum=100)
+    assert_occupancy_parity(outs[15][1], ref)
