@@ -171,6 +171,21 @@ int psfs_fuse(psfs_plan *plan, const float *lmap_dev, float *posterior_dev, uint
 int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev,
                      uint8_t *occ_dev, void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as psfs_reconstruct, bit for bit, with the likelihood maps in a
+ * static device array of the library instead of a workspace argument. The
+ * array holds PSFS_STATIC_SCRATCH_BYTES on every GPU the library runs this
+ * call on, from the first call on that GPU until the process ends; the call
+ * itself allocates nothing. Plans whose maps need more
+ * (psfs_workspace_bytes > PSFS_STATIC_SCRATCH_BYTES) get PSFS_E_RANGE before
+ * anything is enqueued. All calls on one GPU share its array: two calls whose
+ * work overlaps on that GPU (different streams, or graph replays running
+ * concurrently) race on the maps; calls ordered on one stream do not. */
+#define PSFS_STATIC_SCRATCH_BYTES (48u << 20)
+int psfs_reconstruct_static(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev,
+                            uint8_t *occ_dev, void *stream);
+
 /* One step of a frame sequence seen by one rig, as one launch: the
  * likelihood maps of the next frame (Eq. 1-2, as psfs_likelihood of
  * images_dev into lmap_next_dev) and the fusion of the current frame (Eq. 3-9,

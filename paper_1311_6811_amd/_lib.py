@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(PKG, "libpsfs.so")
 
 MAX_VIEWS = 16
 FG_BINS = 4096
+STATIC_SCRATCH_BYTES = 48 << 20          # PSFS_STATIC_SCRATCH_BYTES
 CYLINDERS = 10
 NEAREST, BILINEAR = 0, 1
 
@@ -73,6 +74,7 @@ SIGNATURES = {
     "psfs_likelihood": (C.c_int, [vp, C.POINTER(vp), vp, vp]),
     "psfs_fuse": (C.c_int, [vp, vp, vp, vp, vp]),
     "psfs_reconstruct": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, C.c_size_t, vp]),
+    "psfs_reconstruct_static": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp]),
     "psfs_pipeline_step": (C.c_int, [vp, C.POINTER(vp), vp, vp, vp, vp, vp]),
     "psfs_pipeline_step_pair": (C.c_int, [vp, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, vp, vp, vp, vp]),
     "psfs_pipeline_step_quad": (C.c_int, [vp, C.POINTER(vp), vp, vp, C.POINTER(vp), C.POINTER(vp), vp]),

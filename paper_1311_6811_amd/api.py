@@ -212,6 +212,16 @@ class Plan:
                                          ws.numel(), _stream()))
         return post, occ
 
+    def reconstruct_static(self, images: Sequence[torch.Tensor], posterior=None, occ=None,
+                           want_occ=True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+        """reconstruct() with the likelihood maps in the library's static
+        device array (psfs_reconstruct_static: for callers that cannot
+        allocate; pass preallocated outputs to allocate nothing)."""
+        ims = self._images(images)
+        post, occ, pp, op = self._outputs(posterior, occ, want_occ)
+        L.check(L.lib().psfs_reconstruct_static(self._h, ims, pp, op, _stream()))
+        return post, occ
+
     def new_lmap(self) -> torch.Tensor:
         return torch.empty(max(self.lmap_floats(), 4), dtype=torch.float32, device="cuda")
 

@@ -295,6 +295,38 @@ using namespace psfs;
 using namespace psfs::host;
 
 
+// Likelihood maps of psfs_reconstruct_static: one array per GPU, in the code
+// object, for callers that cannot allocate. In host code `scratch` names a
+// host-side stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) float scratch[PSFS_STATIC_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[256] = {};          // device address of `scratch` per device ordinal
+
+// Address of `scratch` on the current device (looked up on its first use there).
+int static_scratch(float **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 256) return fail(PSFS_E_DEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static scratch array");
+        if (!ptr) return fail(PSFS_E_HIP, "hipGetSymbolAddress returned no address for the static scratch array");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = static_cast<float *>(g_scratch_dev[dev]);
+    return PSFS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int psfs_version(void) { return PSFS_VERSION; }
@@ -481,6 +513,30 @@ int psfs_reconstruct(psfs_plan *plan, const uint8_t *const *images_dev, float *p
         return fail(PSFS_E_WORKSPACE, "workspace needs %zu bytes, 16-byte aligned (got %zu)", need, workspace_bytes);
     if (nvox(plan->grid) == 0) return PSFS_OK;
     float *lmap = static_cast<float *>(workspace_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = enqueue_likelihood(plan, images_dev, lmap, s))) return rc;
+    return enqueue_fuse(plan, lmap, posterior_dev, occ_dev, s);
+    PSFS_GUARD_END
+}
+
+int psfs_reconstruct_static(psfs_plan *plan, const uint8_t *const *images_dev, float *posterior_dev,
+                            uint8_t *occ_dev, void *stream)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_backgrounds(plan);
+    if (rc) return rc;
+    if ((rc = need_grid(plan))) return rc;
+    if ((rc = check_images(plan, images_dev))) return rc;
+    if (nvox(plan->grid) > 0 && (!posterior_dev || !aligned(posterior_dev, 16)))
+        return fail(PSFS_E_ARG, "posterior must be a 16-byte aligned device pointer");
+    const size_t need = psfs_workspace_bytes(plan);
+    if (need > PSFS_STATIC_SCRATCH_BYTES)
+        return fail(PSFS_E_RANGE, "the likelihood maps need %zu bytes; the static scratch holds %zu (use psfs_reconstruct)",
+                    need, static_cast<size_t>(PSFS_STATIC_SCRATCH_BYTES));
+    if (nvox(plan->grid) == 0) return PSFS_OK;
+    if ((rc = check_device())) return rc;
+    float *lmap = nullptr;
+    if ((rc = static_scratch(&lmap))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = enqueue_likelihood(plan, images_dev, lmap, s))) return rc;
     return enqueue_fuse(plan, lmap, posterior_dev, occ_dev, s);

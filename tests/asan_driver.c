@@ -61,6 +61,8 @@ int main(void)
     CALL(psfs_fuse(p, NULL, NULL, NULL, NULL));
     CALL(psfs_fuse(p, (const float *)fk, (float *)((char *)fk + 4), NULL, NULL));
     CALL(psfs_reconstruct(p, imgs, (float *)fk, NULL, fk, 16, NULL));
+    CALL(psfs_reconstruct_static(p, imgs, (float *)fk, NULL, NULL));
+    CALL(psfs_reconstruct_static(NULL, imgs, (float *)fk, NULL, NULL));
     CALL(psfs_pipeline_step(p, imgs, (float *)fk, (const float *)fk, (float *)fk, NULL, NULL));
     CALL(psfs_pipeline_step(p, NULL, NULL, NULL, NULL, (uint8_t *)fk, NULL));
     CALL(psfs_threshold(NULL, -3, 0.5f, NULL, NULL));

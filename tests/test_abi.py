@@ -453,3 +453,19 @@ def test_input_check_validation_without_device(lib):
     assert lib.psfs_input_status(h) == -3
     assert lib.psfs_input_status(None) == -1
     lib.psfs_plan_destroy(h)
+
+
+def test_reconstruct_static_validation_without_device(lib):
+    h = _plan(lib)
+    one = L.ptr_array([0x100000])
+    assert lib.psfs_reconstruct_static(None, one, None, None, None) == -1
+    assert lib.psfs_reconstruct_static(h, one, C.c_void_p(0x300000), None, None) == -3     # nothing set
+    big = (L.psfs_camera * 1)(_cam(8192, 4096))                                            # 128 MiB of maps
+    assert lib.psfs_set_cameras(h, 1, big) == 0
+    assert lib.psfs_set_background(h, 0, C.c_void_p(0x100000), C.c_void_p(0x100000)) == 0
+    g = psfs.make_grid(4, 4, 4, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    assert lib.psfs_reconstruct_static(h, one, C.c_void_p(0x300004), None, None) == -1     # misaligned posterior
+    assert lib.psfs_reconstruct_static(h, one, C.c_void_p(0x300000), None, None) == -2     # beyond the static array
+    assert "static scratch" in lib.psfs_last_error().decode()
+    lib.psfs_plan_destroy(h)
