@@ -6,16 +6,25 @@ of the next four frames (Eq. 1-2; the four frames share the rig and the
 background model, which is read once for them) beside the projection +
 gather + fusion + posterior + threshold of every voxel of the current four
 frames (Eq. 3-9), from the maps the previous launch wrote. Inputs are
-resident in HBM before the timed region; steps rotate over several
-independent slots (each with its own images and background model) so the
-working set exceeds the 256 MB Infinity Cache and every step streams its
-inputs from HBM. The one-frame and two-frame pipelined steps and the
-two-launch single-frame path (likelihood, then fusion) are timed beside it.
+resident in HBM before the timed region. Steps rotate over several
+independent slots, each a four-frame sequence rendered against its own
+background model, so the working set exceeds the 256 MB Infinity Cache and
+every step streams its inputs from HBM.
+
+Timing: exactly --steps launches are captured into one HIP graph; after
+--warmup untimed steps and one untimed pass, --replays passes are timed one
+by one with HIP events on the launch stream, and the median (with min and max)
+per step is reported. The one- and two-frame pipelined steps, the two-launch
+single-frame path, the 256^3 x 12-view 1280x720 sixteen-frame sequence, the
+differentiable pass, the uneven 64-frame batch and the later-stage kernels are
+timed the same way beside it, and a device copy measures the achievable HBM
+bandwidth.
 
 Prints one JSON line (the contract of the driver) with the headline value,
-the dominant kernel's roofline figure and the FP64 CPU oracle's rate.
+the dominant kernel's roofline figure and the FP64 CPU oracle's rate (at one
+thread and at all host threads).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--slots S] [--eager]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--replays R] [--slots S] [--eager]
 """
 from __future__ import annotations
 
@@ -40,16 +49,17 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
 # HBM traffic of one pipe_quad_kernel launch on this workload from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
 # dispatches of `bench.py --steps 24 --warmup 6 --no-cpu --no-batch --no-diff
-# --calibrate-copy`), each scaled by what the counter reads for the calibration
-# kernel (torch.neg over 256 MiB: FETCH_SIZE 131080 KiB for 262144 KiB read,
-# x2.0; WRITE_SIZE 262144 KiB for 262144 KiB written, x1.0). The figures hold
-# for the kernel sources they were taken on (SHA-256 of the files below); once
-# those change, traffic is reported as null until the counters are taken again.
+# --no-c2 --calibrate-copy`), each scaled by what the counter reads for the
+# calibration kernel (torch.neg over 256 MiB: FETCH_SIZE 131080 KiB for 262144
+# KiB read, x2.0; WRITE_SIZE 262144 KiB for 262144 KiB written, x1.0). The
+# figures hold for the kernel sources they were taken on (SHA-256 of the files
+# below); once those change, traffic is reported as null until the counters
+# are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "56f3ce75017acfb7521604de7fd1953c250818482bab65f95edbbb675ac4c36f",
-                 "fetch_kib": 59770.2, "fetch_scale": 2.0, "write_kib": 80504.0, "write_scale": 1.0,
-                 "l2_hit_rate": 0.763}
+PIPE_COUNTERS = {"sources_sha256": "a9d04a276150d08860c518226d09bc1015fabb26e4d23885b2a1ab9dda2e3157",
+                 "fetch_kib": 59692.2, "fetch_scale": 2.0, "write_kib": 80502.9, "write_scale": 1.0,
+                 "l2_hit_rate": 0.668}
 
 
 def sources_sha256() -> str:

@@ -35,6 +35,8 @@ struct psfs_batch {
     std::vector<BatchView> views;           // device table image (cost order)
     std::vector<BatchFrame> frames;
     int64_t nchunks = 0, nbricks = 0, map_floats = 0;
+    int nstages = 0;                        // frame groups of the staged launches
+    int64_t stage_chunk[kBatchMaxStages + 1] = {}, stage_brick[kBatchMaxStages + 1] = {};
     void *dtable = nullptr;
     void *staging = nullptr;                // pinned host image of dtable
     size_t dtable_bytes = 0;
@@ -144,12 +146,40 @@ void build_table(psfs_batch *b)
     b->nchunks = chunk;
     b->nbricks = brick;
     b->map_floats = map_off;
+    // Frame groups of the staged launches: consecutive frames of the table
+    // with about equal shares of the combined cost (voxel-views plus 4.4 per
+    // pixel: the measured ratio of likelihood time per pixel to fusion time
+    // per voxel-view), so that each launch's likelihood and fusion halves are
+    // of similar length.
+    b->nstages = std::min(kBatchMaxStages, nf);
+    std::vector<double> cum(nf + 1, 0.0);
+    for (int oi = 0; oi < nf; ++oi) {
+        const psfs_frame &u = b->user[b->order[oi]];
+        double px = 0.0;
+        for (int k = 0; k < u.n; ++k) px += static_cast<double>(b->cams[b->cam0[b->order[oi]] + k].width) *
+                                           b->cams[b->cam0[b->order[oi]] + k].height;
+        const double vv = static_cast<double>(u.grid.nx) * u.grid.ny * u.grid.nz * u.n;
+        cum[oi + 1] = cum[oi] + vv + 4.4 * px;
+    }
+    int f0 = 0;
+    for (int g = 0; g <= b->nstages; ++g) {
+        int fe = nf;
+        if (g < b->nstages) {
+            const double target = cum[nf] * g / b->nstages;
+            fe = f0;
+            while (fe < nf && cum[fe] < target) ++fe;
+        }
+        // first chunk / brick of frame fe (or the totals past the last frame)
+        b->stage_brick[g] = fe < nf ? b->frames[fe].brick0 : b->nbricks;
+        b->stage_chunk[g] = fe < nf ? b->views[b->frames[fe].view0].chunk0 : b->nchunks;
+        f0 = fe;
+    }
     b->dirty = true;
 }
 
 size_t workspace_bytes(const psfs_batch *b)
 {
-    return align256(static_cast<size_t>(b->map_floats) * sizeof(float)) + 256;
+    return align256(static_cast<size_t>(b->map_floats) * sizeof(float)) + kBatchCounterBytes;
 }
 
 void drop_graph(psfs_batch *b)
@@ -179,6 +209,11 @@ BatchArgs make_args(const psfs_batch *b, void *ws)
     const double pr = b->params.prior;
     a.L0 = static_cast<float>(std::log(pr / (1.0 - pr)));
     a.tau = b->params.threshold;
+    a.nstages = b->nstages;
+    for (int g = 0; g <= kBatchMaxStages; ++g) {
+        a.stage_chunk[g] = b->stage_chunk[g];
+        a.stage_brick[g] = b->stage_brick[g];
+    }
     return a;
 }
 
@@ -225,11 +260,21 @@ int check_run_args(psfs_batch *b, void *ws, size_t bytes)
     return PSFS_OK;
 }
 
-int run_eager(psfs_batch *b, void *ws, hipStream_t s)
+// The launches of one run: staged (tiles of 256 lanes) or likelihood then fusion.
+hipError_t enqueue_batch(const psfs_batch *b, void *ws, hipStream_t s)
 {
+    if (batch_staged_tile(b->tile)) {
+        const int grid = std::max(1, b->cus * batch_stage_occupancy(b->tile, b->params.sampling));
+        return launch_batch_staged(make_args(b, ws), b->tile, b->params.sampling, grid, s);
+    }
     int sg, fg;
     grids(b, sg, fg);
-    hipError_t e = launch_batch(make_args(b, ws), b->tile, b->params.sampling, sg, fg, s);
+    return launch_batch(make_args(b, ws), b->tile, b->params.sampling, sg, fg, s);
+}
+
+int run_eager(psfs_batch *b, void *ws, hipStream_t s)
+{
+    hipError_t e = enqueue_batch(b, ws, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return PSFS_OK;
 }
@@ -406,9 +451,7 @@ int psfs_batch_run(psfs_batch *b, void *workspace_dev, size_t workspace_bytes_, 
         drop_graph(b);
         e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int sg, fg;
-        grids(b, sg, fg);
-        hipError_t le = launch_batch(make_args(b, workspace_dev), b->tile, b->params.sampling, sg, fg, s);
+        hipError_t le = enqueue_batch(b, workspace_dev, s);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s, &g);
         if (le != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(le, "batch launch during capture"); }

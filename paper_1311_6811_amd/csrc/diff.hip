@@ -319,19 +319,27 @@ __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
     }
 }
 
-// loss = inv_count * sum of the workgroup partials (one workgroup, fixed order).
+// loss = inv_count * sum of the workgroup partials, in a fixed order: thread
+// t adds partials t + 256 q (eight loads in flight at a time), then the
+// wave butterfly of wave_sum, then the four waves in order.
 __global__ __launch_bounds__(256) void loss_finalize_kernel(const double *part, int64_t nparts, float inv_count, float *loss)
 {
-    __shared__ double buf[256];
+    __shared__ double wsum[4];
     double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nparts; b += 256) s += part[b];
-    buf[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (static_cast<int>(threadIdx.x) < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-        __syncthreads();
+    for (int64_t b0 = 0; b0 < nparts; b0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t b = b0 + threadIdx.x + 256 * q;
+            v[q] = b < nparts ? part[b] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += v[q];
     }
-    if (threadIdx.x == 0) *loss = static_cast<float>(buf[0] * static_cast<double>(inv_count));
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *loss = static_cast<float>(((wsum[0] + wsum[1]) + (wsum[2] + wsum[3])) * static_cast<double>(inv_count));
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(float *p, int64_t n4)
@@ -462,20 +470,34 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
     }
 }
 
-// gP[e] = sum over workgroups of cam_part[b][e], FP64, fixed order. One workgroup per entry.
-__global__ __launch_bounds__(256) void cam_finalize_kernel(const float *part, int64_t nparts, int ne, float *gP)
+// The 12 camera-gradient entries of view v: gP[12v + e] = sum over the
+// backward workgroups b of cam_part[b][12v + e], in FP64 and a fixed order
+// (thread t adds b = t, t + 256, ...; then wave butterflies; then the four
+// waves in order). Run by one 256-lane workgroup per view of the pixel chain,
+// which follows the backward kernel on the stream.
+__device__ __forceinline__ void camera_gradient(const ChainArgs &a, int v)
 {
-    __shared__ double buf[256];
-    const int e = blockIdx.x;
-    double s = 0.0;
-    for (int64_t b = threadIdx.x; b < nparts; b += 256) s += static_cast<double>(part[b * ne + e]);
-    buf[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if (static_cast<int>(threadIdx.x) < w) buf[threadIdx.x] += buf[threadIdx.x + w];
-        __syncthreads();
+    __shared__ double wsum[kWaves][12];
+    const int ne = a.n * 12;
+    double acc[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) acc[e] = 0.0;
+    for (int64_t b = threadIdx.x; b < a.cam_parts; b += 256) {
+        const float *row = a.cam_part + b * ne + v * 12;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) acc[e] += static_cast<double>(row[e]);
     }
-    if (threadIdx.x == 0) gP[e] = static_cast<float>(buf[0]);
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        const double w = wave_sum(acc[e]);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6][e] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        double sum = 0.0;
+        for (int w = 0; w < kWaves; ++w) sum += wsum[w][threadIdx.x];
+        a.gP[v * 12 + threadIdx.x] = static_cast<float>(sum);
+    }
 }
 
 __device__ __forceinline__ void chain_pixel(float A, float i0, float i1, float i2, const float m[3], const float v[3],
@@ -494,6 +516,7 @@ __device__ __forceinline__ void chain_pixel(float A, float i0, float i1, float i
 
 __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
 {
+    if (blockIdx.x == 0) camera_gradient(a, static_cast<int>(blockIdx.y));
     const ChainView cv = a.view[blockIdx.y];
     const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
     if (p0 >= cv.npix) return;
@@ -565,11 +588,14 @@ hipError_t launch_diff_backward(const DiffArgs &a, const ChainArgs &c, int64_t m
     const int64_t nb = diff_bwd_blocks(a.nx, a.ny, a.nz);
     if (nb > 0 && a.n > 0) hipLaunchKernelGGL(diff_bwd_kernel, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, a);
     if (a.n > 0) {
-        hipLaunchKernelGGL(cam_finalize_kernel, dim3(a.n * 12), dim3(256), 0, s, a.cam_part,
-                           (nb > 0 ? nb : 0), a.n * 12, gP);
+        // the pixel chain also sums the camera-gradient partials (camera_gradient)
+        ChainArgs ca = c;
+        ca.cam_part = a.cam_part;
+        ca.cam_parts = nb > 0 ? nb : 0;
+        ca.gP = gP;
         const int64_t quads = (max_npix + 3) / 4;
         hipLaunchKernelGGL(pixel_chain_kernel, dim3(static_cast<unsigned>((quads + 255) / 256), static_cast<unsigned>(c.n)),
-                           dim3(256), 0, s, c);
+                           dim3(256), 0, s, ca);
     }
     return hipGetLastError();
 }

@@ -183,7 +183,8 @@ __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImage
         float *const post[4] = {f.post, qo.post[0], qo.post[1], qo.post[2]};
         uint8_t *const occ[4] = {f.occ, qo.occ[0], qo.occ[1], qo.occ[2]};
         fuse_column_quad<TX, KZ>([&](int v) -> const ViewGeom & { return f.view[v]; }, f.n, f.lmap, gd, i, j,
-                                 static_cast<int>(zc) * KZ, f.L0, f.tau, post, occ);
+                                 static_cast<int>(zc) * KZ, f.L0, f.tau, post, occ,
+                                 reinterpret_cast<float *>(&stage[threadIdx.x >> 6]));
     }
 }
 

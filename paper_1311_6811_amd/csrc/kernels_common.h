@@ -140,10 +140,10 @@ __device__ __forceinline__ void report_wave(const InputCheck &chk, bool bad)
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(chk.flags, chk.bit);
 }
 
-// LDS of one wave in slm_wave: 192 16-byte vectors (means, then variances)
-// and 192 image words.
+// LDS of one wave in slm_wave: 192 16-byte vectors (means, then variances;
+// slm_wave_quad uses all 256 to regroup its results) and 192 image words.
 struct SlmStage {
-    f32x4 f[3 * 64];
+    f32x4 f[4 * 64];
     uint32_t w[3 * 64];
 };
 
@@ -251,7 +251,8 @@ __device__ __forceinline__ void slm_wave_tail(const uint8_t *img, const float *m
 // background model once.
 
 // slm_wave for two frames: the means and variances are loaded once; lane l
-// writes pixels p0 + 4l .. p0 + 4l + 3 of both frames with two 16-byte stores.
+// converts pixels p0 + 4l .. p0 + 4l + 3 of both frames, and the results leave
+// in two lane-contiguous 16-byte stores.
 __device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_t *img_b, const float *mean,
                                               const float *var, float *out2, int64_t p0, float k0, SlmStage &st,
                                               const float *fg, InputCheck chk)
@@ -303,9 +304,14 @@ __device__ __forceinline__ void slm_wave_pair(const uint8_t *img_a, const uint8_
     }
     const f32x4 ra = quad_log2slm(qa, quad_k0(qa, k0, fg));
     const f32x4 rb = quad_log2slm(qb, quad_k0(qb, k0, fg));
-    f32x4 *o = reinterpret_cast<f32x4 *>(out2 + 2 * (p0 + 4 * lane));
-    o[0] = f32x4{ra.x, rb.x, ra.y, rb.y};
-    o[1] = f32x4{ra.z, rb.z, ra.w, rb.w};
+    // regrouped through LDS so that each store instruction of the wave writes
+    // one contiguous kilobyte (the stage's reads above are ordered before)
+    st.f[2 * lane] = f32x4{ra.x, rb.x, ra.y, rb.y};
+    st.f[2 * lane + 1] = f32x4{ra.z, rb.z, ra.w, rb.w};
+    wave_lds_sync();
+    f32x4 *o = reinterpret_cast<f32x4 *>(out2 + 2 * p0);
+    o[lane] = st.f[lane];
+    o[64 + lane] = st.f[64 + lane];
 }
 
 // slm_wave_tail for two frames.
@@ -332,8 +338,8 @@ __device__ __forceinline__ void slm_wave_pair_tail(const uint8_t *img_a, const u
 
 // slm_wave for four frames: the means and variances are loaded once and
 // regrouped once; the four images' words are regrouped one after another
-// through the same LDS words. Lane l writes pixels p0 + 4l .. p0 + 4l + 3 of
-// the four frames with four 16-byte stores.
+// through the same LDS words. Lane l converts pixels p0 + 4l .. p0 + 4l + 3 of
+// the four frames; the results leave in four lane-contiguous 16-byte stores.
 __device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], const float *mean, const float *var,
                                               float *out4, int64_t p0, float k0, SlmStage &st, const float *fg,
                                               InputCheck chk)
@@ -397,11 +403,17 @@ __device__ __forceinline__ void slm_wave_quad(const uint8_t *const (&img)[4], co
         for (int r = 0; r < 3; ++r) q.w[r] = qw[f][r];
         res[f] = quad_log2slm(q, quad_k0(q, k0, fg));
     }
-    f32x4 *o = reinterpret_cast<f32x4 *>(out4 + 4 * (p0 + 4 * lane));
-    o[0] = f32x4{res[0].x, res[1].x, res[2].x, res[3].x};
-    o[1] = f32x4{res[0].y, res[1].y, res[2].y, res[3].y};
-    o[2] = f32x4{res[0].z, res[1].z, res[2].z, res[3].z};
-    o[3] = f32x4{res[0].w, res[1].w, res[2].w, res[3].w};
+    // Regroup through LDS so that each store instruction of the wave writes
+    // one contiguous kilobyte (64 lanes x one pixel's four frames): pixel e of
+    // the wave (entry e of the stage) goes out from lane e % 64.
+    st.f[4 * lane + 0] = f32x4{res[0].x, res[1].x, res[2].x, res[3].x};
+    st.f[4 * lane + 1] = f32x4{res[0].y, res[1].y, res[2].y, res[3].y};
+    st.f[4 * lane + 2] = f32x4{res[0].z, res[1].z, res[2].z, res[3].z};
+    st.f[4 * lane + 3] = f32x4{res[0].w, res[1].w, res[2].w, res[3].w};
+    wave_lds_sync();
+    f32x4 *o = reinterpret_cast<f32x4 *>(out4 + 4 * p0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o[64 * s + lane] = st.f[64 * s + lane];
 }
 
 // slm_wave_tail for four frames.
@@ -441,30 +453,46 @@ __device__ __forceinline__ float bilinear_sample(const float *map, int W, int H,
 
 // Tile t of an ntx x nty x nzc tile grid taken octant by octant: the grid is
 // halved along each axis (first halves rounded up), the eight octants follow
-// one another, and each octant's tiles run z-major inside it. With
-// contiguous per-XCD tile ranges (xcd_remap, the pipelined launches), an XCD works on
-// one compact block of the grid (one octant when the tile count splits
-// evenly), whose projections cover smaller image areas than a z-slab of the
-// whole grid. A bijection for every grid shape (empty octants are skipped).
+// one another, and an octant of more than kOctantLeaf tiles is split the same
+// way again; the tiles of a leaf block run z-major. With contiguous per-XCD
+// tile ranges (xcd_remap, the pipelined launches), an XCD works on one
+// compact block of the grid (one octant when the tile count splits evenly),
+// and the workgroups it runs at a time on a few neighbouring leaf blocks, whose
+// projections cover smaller image areas than a z-slab of the block. (At 256^3
+// voxels x 12 views of 1280x720, four frames per launch, splitting octants
+// down to 256 tiles took a launch from 582 to 519 us; one level serves the
+// 128^3 grid's 2048 tiles.) A bijection for every grid shape (empty octants
+// are skipped).
+constexpr uint32_t kOctantLeaf = 256;
+
 __device__ __forceinline__ void octant_tile(uint32_t t, uint32_t ntx, uint32_t nty, uint32_t nzc, uint32_t &txi,
                                             uint32_t &tyi, uint32_t &zc)
 {
-    const uint32_t hx = (ntx + 1) / 2, hy = (nty + 1) / 2, hz = (nzc + 1) / 2;
-    uint32_t o = 0, sx = hx, sy = hy, sz = hz;
-    for (; o < 8; ++o) {
-        sx = (o & 1) ? ntx - hx : hx;
-        sy = (o & 2) ? nty - hy : hy;
-        sz = (o & 4) ? nzc - hz : hz;
-        const uint32_t cnt = sx * sy * sz;
-        if (t < cnt) break;
-        t -= cnt;
-    }
+    uint32_t bx = 0, by = 0, bz = 0, sx = ntx, sy = nty, sz = nzc;
+    do {
+        const uint32_t hx = (sx + 1) / 2, hy = (sy + 1) / 2, hz = (sz + 1) / 2;
+        uint32_t o = 0, cx = hx, cy = hy, cz = hz;
+        for (; o < 8; ++o) {
+            cx = (o & 1) ? sx - hx : hx;
+            cy = (o & 2) ? sy - hy : hy;
+            cz = (o & 4) ? sz - hz : hz;
+            const uint32_t cnt = cx * cy * cz;
+            if (t < cnt) break;
+            t -= cnt;
+        }
+        bx += (o & 1) ? hx : 0;
+        by += (o & 2) ? hy : 0;
+        bz += (o & 4) ? hz : 0;
+        sx = cx;
+        sy = cy;
+        sz = cz;
+    } while (sx * sy * sz > kOctantLeaf);
     const uint32_t plane = sx * sy;
     const uint32_t lz = t / plane, r = t - lz * plane;
     const uint32_t ly = r / sx, lx = r - ly * sx;
-    txi = ((o & 1) ? hx : 0) + lx;
-    tyi = ((o & 2) ? hy : 0) + ly;
-    zc = ((o & 4) ? hz : 0) + lz;
+    txi = bx + lx;
+    tyi = by + ly;
+    zc = bz + lz;
 }
 
 // Workgroups are dispatched round-robin over the XCDs; give each XCD one
@@ -764,7 +792,7 @@ __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, cons
 template <int TX, int KZ, class Views>
 __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, const float *lmap4, const GridDesc &a,
                                                  int i, int j, int k0, float L0, float tau, float *const (&post)[4],
-                                                 uint8_t *const (&occ)[4])
+                                                 uint8_t *const (&occ)[4], float *wave_stage)
 {
     const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
     const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
@@ -822,6 +850,55 @@ __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, cons
             L[kk][2] += val[kk].z;
             L[kk][3] += val[kk].w;
         }
+    }
+    // A wave whose 32 x 2 x KZ voxels all lie in the grid, with rows that
+    // start 16-byte aligned, regroups its outputs through LDS so that each
+    // store instruction writes whole 16-byte pieces of rows (8 rows of 32
+    // posteriors, or 4 frames x 8 rows of 32 occupancy bytes): one cache
+    // access per 64 bytes, where per-voxel stores cost one per 4 lanes.
+    static_assert(TX != 32 || KZ == 4, "the regrouped stores cover 32 x 2 x 4 voxels");
+    bool aligned_rows = TX == 32 && (a.nx & 15) == 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        aligned_rows = aligned_rows && (reinterpret_cast<uintptr_t>(post[f]) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(occ[f]) & 15) == 0;
+    if (aligned_rows && i_lo + 31 < a.nx && j_lo + 1 < a.ny && k0 + KZ - 1 < a.nz) {
+        // stage entry (f * KZ + kk) * 64 + lane: voxel (i_lo + lane % 32, j_lo + lane / 32, k0 + kk), frame f
+        uint8_t *stage_b = reinterpret_cast<uint8_t *>(wave_stage);
+        uint32_t ob[KZ];
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            ob[kk] = 0;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float p = sigmoid_fast(L[kk][f]);
+                wave_stage[(f * KZ + kk) * 64 + lane] = p;
+                ob[kk] |= (p > tau ? 1u : 0u) << (8 * f);
+            }
+        }
+        wave_lds_sync();
+        const int r = lane >> 3, c = lane & 7;           // row r = (kk, y) = (r / 2, r % 2), 16-byte piece c
+        const int64_t row = (static_cast<int64_t>(k0 + (r >> 1)) * a.ny + j_lo + (r & 1)) * a.nx + i_lo;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            *reinterpret_cast<f32x4 *>(post[f] + row + 4 * c) =
+                *reinterpret_cast<const f32x4 *>(wave_stage + (f * KZ + (r >> 1)) * 64 + (r & 1) * 32 + 4 * c);
+        wave_lds_sync();
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) stage_b[(f * KZ + kk) * 64 + lane] = static_cast<uint8_t>(ob[kk] >> (8 * f));
+        wave_lds_sync();
+        {
+            // lane l: frame l / 16, row (l / 2) % 8, half l % 2 of the row's 32 bytes
+            const int f = lane >> 4, rr = (lane >> 1) & 7, half = lane & 1;
+            const int64_t orow = (static_cast<int64_t>(k0 + (rr >> 1)) * a.ny + j_lo + (rr & 1)) * a.nx + i_lo;
+            uint8_t *const dst = f == 0 ? occ[0] : f == 1 ? occ[1] : f == 2 ? occ[2] : occ[3];
+            if (dst)
+                *reinterpret_cast<f32x4 *>(dst + orow + 16 * half) =
+                    *reinterpret_cast<const f32x4 *>(stage_b + (f * KZ + (rr >> 1)) * 64 + (rr & 1) * 32 + 16 * half);
+        }
+        return;
     }
     if (i >= a.nx || j >= a.ny) return;
     const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;

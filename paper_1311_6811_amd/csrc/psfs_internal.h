@@ -127,6 +127,9 @@ struct ChainArgs {
     ChainView view[kMaxViews];
     const float *adj;                   // int64 fixed-point adjoint maps (see diff.hip)
     const float *grad_loss;
+    const float *cam_part;              // [cam_parts][n][12] partial camera gradients of the backward workgroups
+    int64_t cam_parts;
+    float *gP;                          // [n][12] camera-matrix gradients
     float inv_count;
     float k0;
     int32_t n;
@@ -150,15 +153,25 @@ struct BatchFrame {
     uint8_t *occ;                       // nullable
 };
 
+constexpr int kBatchMaxStages = 4;      // frame groups of a staged batch
+
 struct BatchArgs {
     const BatchView *views;
     const BatchFrame *frames;           // decreasing cost order
     float *lmap;
-    unsigned long long *counters;       // work counters (a 256-byte region), reset by the first launch
+    unsigned long long *counters;       // work counters (a kBatchCounterBytes region), reset by the first launch
     int64_t nchunks, nbricks;
     int32_t nviews, nframes;
     float k0, L0, tau;
+    // Staged launches: the frames (in table order) form nstages groups; group
+    // g owns likelihood chunks [stage_chunk[g], stage_chunk[g+1]) and fusion
+    // bricks [stage_brick[g], stage_brick[g+1]). Launch s runs group s's
+    // likelihood beside group s-1's fusion.
+    int32_t nstages;
+    int64_t stage_chunk[kBatchMaxStages + 1];
+    int64_t stage_brick[kBatchMaxStages + 1];
 };
+constexpr size_t kBatchCounterBytes = 512;
 
 // Smoothing, threshold and surface extraction of one posterior grid.
 struct SurfArgs {
@@ -225,6 +238,11 @@ int64_t batch_chunk_pixels();
 int64_t batch_bricks(int nx, int ny, int nz, int tile);
 int batch_fuse_occupancy(int tile, int sampling);
 hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid, int fuse_grid, hipStream_t s);
+// Staged variant (tiles of 256 lanes): a counter reset, then nstages + 1
+// launches of batch_stage_kernel with `grid` workgroups each.
+bool batch_staged_tile(int tile);
+int batch_stage_occupancy(int tile, int sampling);
+hipError_t launch_batch_staged(const BatchArgs &a, int tile, int sampling, int grid, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 int64_t surface_blocks(int64_t nvox);
 hipError_t launch_colour(const ColourArgs &a, hipStream_t s);

@@ -176,3 +176,45 @@ def test_batch_with_the_largest_grid():
         post, occ = single(fr, bf)
         torch.cuda.synchronize()
         assert torch.equal(post, bf.posterior) and torch.equal(occ, bf.occ)
+
+
+def test_every_tile_keeps_the_bits(mixed):
+    """Each tile (the staged launches for 256-lane tiles, likelihood then
+    fusion for the 128-lane one) gives every frame the bits of the frame
+    alone."""
+    frames, bfs = mixed
+    refs = []
+    for fr, bf in zip(frames[:7], bfs[:7]):
+        post, occ = single(fr, bf)
+        refs.append((post, occ))
+    torch.cuda.synchronize()
+    b = psfs.Batch(bfs[:7])
+    for t in range(len(psfs.tiles())):
+        say(f"  tile {t}: {psfs.tiles()[t]}")
+        b.set_tile(t)
+        for bf in bfs[:7]:
+            bf.posterior.fill_(-1.0)
+            bf.occ.fill_(7)
+        b.run()
+        torch.cuda.synchronize()
+        for (post, occ), bf in zip(refs, bfs[:7]):
+            assert torch.equal(post, bf.posterior) and torch.equal(occ, bf.occ)
+
+
+def test_whole_64_frame_batch_bitwise_equals_single_frames():
+    """The whole uneven 64-frame workload (grid edge 64-192, 4-12 views, three
+    image sizes) as one batch: every frame bit-identical to the frame
+    reconstructed alone."""
+    from concurrent.futures import ThreadPoolExecutor
+    say("batch: the whole 64-frame uneven workload")
+    with ThreadPoolExecutor(8) as ex:
+        frames = list(ex.map(lambda f: S.config_frame(3, f), range(64)))
+    bfs = [to_batch_frame(fr) for fr in frames]
+    b = psfs.Batch(bfs)
+    b.run()
+    b.run()                                   # the graph replay after the capturing run
+    torch.cuda.synchronize()
+    for k, (fr, bf) in enumerate(zip(frames, bfs)):
+        post, occ = single(fr, bf)
+        torch.cuda.synchronize()
+        assert torch.equal(post, bf.posterior) and torch.equal(occ, bf.occ), f"frame {k}"
