@@ -48,8 +48,8 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
 
 # HBM traffic of one pipe_quad_kernel launch on this workload from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, averaged over the
-# dispatches of `bench.py --steps 24 --warmup 6 --no-cpu --no-batch --no-diff
-# --no-c2 --calibrate-copy`), each scaled by what the counter reads for the
+# dispatches of `bench.py --steps 24 --warmup 6 --replays 5 --no-cpu --no-batch
+# --no-diff --no-c2 --calibrate-copy`), each scaled by what the counter reads for the
 # calibration kernel (torch.neg over 256 MiB: FETCH_SIZE 131080 KiB for 262144
 # KiB read, x2.0; WRITE_SIZE 262144 KiB for 262144 KiB written, x1.0). The
 # figures hold for the kernel sources they were taken on (SHA-256 of the files
@@ -57,9 +57,9 @@ PAPER_CONTEXT = {"scope": "whole pipeline per frame (reconstruction + colour + t
 # are taken again.
 PIPE_COUNTER_SOURCES = ("paper_1311_6811_amd/csrc/forward.hip", "paper_1311_6811_amd/csrc/kernels_common.h",
                         "paper_1311_6811_amd/csrc/psfs_internal.h")
-PIPE_COUNTERS = {"sources_sha256": "a9d04a276150d08860c518226d09bc1015fabb26e4d23885b2a1ab9dda2e3157",
-                 "fetch_kib": 59692.2, "fetch_scale": 2.0, "write_kib": 80502.9, "write_scale": 1.0,
-                 "l2_hit_rate": 0.668}
+PIPE_COUNTERS = {"sources_sha256": "4f4dbc442daf8d4b5e58565e9f37eaf61380c7751cd2dc38176c60a0b93f4a2b",
+                 "fetch_kib": 59698.5, "fetch_scale": 2.0, "write_kib": 80496.2, "write_scale": 1.0,
+                 "l2_hit_rate": 0.669}
 
 
 def sources_sha256() -> str:
@@ -301,6 +301,21 @@ def main():
           f"(min {t_quad['min'] * 1e3:.2f}, max {t_quad['max'] * 1e3:.2f}) = {ms_quad * 1e3 / 4:.2f} us/frame",
           file=sys.stderr, flush=True)
 
+    # the step's two halves alone: the likelihood rounds (quad maps of the next
+    # four frames, no fusion) and the fusion rounds (no likelihood)
+    def quad_likelihood(i):
+        nx = slots[(i + 1) % S_]
+        nx["plan"].pipeline_step_quad(nx["ims"], maps4[(i + 1) % 2], None, None, None)
+
+    def quad_fusion(i):
+        c = slots[i % S_]
+        c["plan"].pipeline_step_quad(None, None, maps4[i % 2], c["posts"], c["occs"])
+
+    t_ql = T.steps(quad_likelihood, K)
+    t_qf = T.steps(quad_fusion, K)
+    print(f"[bench] four-frame step halves alone: likelihood {t_ql['median'] * 1e3:.2f} us, "
+          f"fusion {t_qf['median'] * 1e3:.2f} us", file=sys.stderr, flush=True)
+
     # ---- two frames per launch (frames 0 and 1 of each slot's sequence)
     maps2 = [slots[0]["plan"].new_lmap_pair(), slots[0]["plan"].new_lmap_pair()]
 
@@ -432,6 +447,9 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes,
                      "frac_of_measured_copy": achieved / bw["copy_GBs"],
                      "l2_hit_rate": PIPE_COUNTERS["l2_hit_rate"] if traffic is not None else None},
+        "four_frame_halves_us": {"likelihood_only": t_ql["median"] * 1e3, "fusion_only": t_qf["median"] * 1e3,
+                                 "likelihood_only_algorithmic_bytes": 36 * npix,
+                                 "fusion_only_algorithmic_bytes": 20 * V},
         "two_frame_step_us": ms_pair * 1e3,
         "two_frame_roofline": {"kernel": "pipe_pair_kernel", "algorithmic_bytes": pair_bytes,
                                "achieved_GBs": pair_bytes / (ms_pair * 1e-3) / 1e9,

@@ -480,7 +480,24 @@ int psfs_batch_tune(psfs_batch *batch, void *workspace_dev, size_t workspace_byt
  * or -1 for the tuned/default choice. */
 int psfs_tile_count(void);
 int psfs_tile_describe(int tile, int32_t *tx, int32_t *ty, int32_t *kz);
+/* Fusion tile of a plan's one-frame paths (psfs_fuse, psfs_reconstruct,
+ * psfs_pipeline_step); -1 = default. The two- and four-frame steps use fixed
+ * tiles. Tiles never change results, only speed. */
 int psfs_set_tile(psfs_plan *plan, int tile);
+int psfs_get_tile(const psfs_plan *plan);     /* the tile in use, or a negative psfs_status */
+
+/* Plan autotuner: computes the plan's likelihood maps of `images_dev` once,
+ * then times the fusion with every tile (2 warm-up + 5 timed launches each,
+ * HIP events on `stream`, blocking) and sets the fastest on the plan. The
+ * choice is cached in the same JSON file as the batch tuner's, keyed by
+ * device, CU count, sampling, grid edge class (ceil log2 of the longest grid
+ * side), view count and image class (ceil log2 of the largest view's pixel
+ * count); a cached choice is applied without timing unless force != 0.
+ * workspace_dev: psfs_tune_workspace_bytes(plan) bytes, 256-byte aligned
+ * (maps, a posterior and an occupancy grid; overwritten). */
+size_t psfs_tune_workspace_bytes(const psfs_plan *plan);
+int psfs_tune(psfs_plan *plan, const uint8_t *const *images_dev, void *workspace_dev, size_t workspace_bytes,
+              void *stream, int force, int *best_tile);
 
 #ifdef __cplusplus
 }

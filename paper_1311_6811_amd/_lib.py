@@ -101,6 +101,9 @@ SIGNATURES = {
     "psfs_tile_count": (C.c_int, []),
     "psfs_tile_describe": (C.c_int, [C.c_int, i32p, i32p, i32p]),
     "psfs_set_tile": (C.c_int, [vp, C.c_int]),
+    "psfs_get_tile": (C.c_int, [vp]),
+    "psfs_tune_workspace_bytes": (C.c_size_t, [vp]),
+    "psfs_tune": (C.c_int, [vp, C.POINTER(vp), vp, C.c_size_t, vp, C.c_int, i32p]),
 }
 
 

@@ -112,6 +112,20 @@ class Plan:
     def set_tile(self, tile: int) -> None:
         L.check(L.lib().psfs_set_tile(self._h, int(tile)))
 
+    @property
+    def tile(self) -> int:
+        return L.check(L.lib().psfs_get_tile(self._h))
+
+    def tune(self, images: Sequence[torch.Tensor], force: bool = False) -> int:
+        """Times the one-frame fusion with every tile on these images (or
+        takes the cached choice) and keeps the fastest; returns its index."""
+        ims = self._images(images)
+        ws = torch.empty(max(int(L.lib().psfs_tune_workspace_bytes(self._h)), 256), dtype=torch.uint8, device="cuda")
+        best = C.c_int32(-1)
+        L.check(L.lib().psfs_tune(self._h, ims, ws.data_ptr(), ws.numel(), _stream(), int(bool(force)),
+                                  C.byref(best)))
+        return int(best.value)
+
     def set_background(self, view: int, mean: torch.Tensor, var: torch.Tensor) -> None:
         c = self.cams[view]
         shape = (c.height, c.width, 3)

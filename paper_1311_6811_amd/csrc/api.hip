@@ -1,6 +1,7 @@
 // Host side of libpsfs: plans, argument validation, workspace layout and
 // kernel launches behind the C ABI of psfs.h. Every entry point validates its
 // arguments before enqueueing anything and never lets an exception escape.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -275,7 +276,10 @@ int prepare_diff(const psfs_plan *p, const uint8_t *const *images, const uint8_t
         return fail(PSFS_E_WORKSPACE, "differentiable workspace needs %zu bytes, 256-byte aligned (got %zu)", L.total, ws_bytes);
     FuseArgs f{};
     fill_geometry(p, PSFS_BILINEAR, f);
-    for (int k = 0; k < p->n; ++k) a.view[k] = f.view[k];
+    for (int k = 0; k < p->n; ++k) {
+        a.view[k] = f.view[k];
+        for (int e = 0; e < 12; ++e) a.Pd[k][e] = static_cast<double>(p->cams[k].P[e]);
+    }
     char *base = static_cast<char *>(ws);
     a.lmap = reinterpret_cast<const float *>(base + L.lmap);
     a.adj = reinterpret_cast<float *>(base + L.adj);
@@ -1004,6 +1008,109 @@ int psfs_set_tile(psfs_plan *plan, int tile)
     if (tile < -1 || tile >= tile_count()) return fail(PSFS_E_RANGE, "tile %d outside -1..%d", tile, tile_count() - 1);
     plan->tile = tile;
     return PSFS_OK;
+}
+
+int psfs_get_tile(const psfs_plan *plan)
+{
+    if (!plan) return fail(PSFS_E_ARG, "plan is NULL");
+    return plan->tile >= 0 ? plan->tile : default_tile();
+}
+
+size_t psfs_tune_workspace_bytes(const psfs_plan *plan)
+{
+    if (!plan || plan->n < 0 || !plan->has_grid) return 0;
+    const size_t v = static_cast<size_t>(nvox(plan->grid));
+    return align256(psfs_workspace_bytes(plan)) + align256(4 * v) + align256(v);
+}
+
+int psfs_tune(psfs_plan *plan, const uint8_t *const *images_dev, void *workspace_dev, size_t workspace_bytes,
+              void *stream, int force, int *best_tile)
+{
+    PSFS_GUARD_BEGIN
+    int rc = need_backgrounds(plan);
+    if (rc) return rc;
+    if ((rc = need_grid(plan))) return rc;
+    if ((rc = check_images(plan, images_dev))) return rc;
+    const size_t need = psfs_tune_workspace_bytes(plan);
+    if (!workspace_dev || workspace_bytes < need || !aligned(workspace_dev, 256))
+        return fail(PSFS_E_WORKSPACE, "tuning workspace needs %zu bytes, 256-byte aligned (got %zu)", need,
+                    workspace_bytes);
+    // cache key: device, CU count, sampling, grid edge class, view count, image class
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    if ((rc = check_device())) return rc;
+    auto log2ceil = [](int64_t x) {
+        int c = 0;
+        while ((int64_t(1) << c) < x) ++c;
+        return c;
+    };
+    int64_t edge = std::max({plan->grid.nx, plan->grid.ny, plan->grid.nz}), px = 1;
+    for (int k = 0; k < plan->n; ++k) px = std::max<int64_t>(px, static_cast<int64_t>(plan->cams[k].width) * plan->cams[k].height);
+    char key[160];
+    std::snprintf(key, sizeof(key), "gfx950/%dcu/plan/s%d/e%d/n%d/i%d", cus, plan->params.sampling, log2ceil(edge),
+                  plan->n, log2ceil(px));
+    const std::string path = tune_cache_path();
+    if (!force) {
+        std::lock_guard<std::mutex> lock(tune_cache_mutex());
+        const auto m = read_tune_cache(path);
+        const auto it = m.find(key);
+        if (it != m.end() && it->second >= 0 && it->second < tile_count()) {
+            plan->tile = it->second;
+            if (best_tile) *best_tile = it->second;
+            return PSFS_OK;
+        }
+    }
+    char *base = static_cast<char *>(workspace_dev);
+    float *lmap = reinterpret_cast<float *>(base);
+    const size_t v = static_cast<size_t>(nvox(plan->grid));
+    float *post = reinterpret_cast<float *>(base + align256(psfs_workspace_bytes(plan)));
+    uint8_t *occ = reinterpret_cast<uint8_t *>(base + align256(psfs_workspace_bytes(plan)) + align256(4 * v));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the maps do not depend on the tile: one likelihood pass, then each tile's fusion
+    if ((rc = enqueue_likelihood(plan, images_dev, lmap, s))) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const int keep = plan->tile;
+    float best_ms = 1e30f;
+    int best = default_tile();
+    for (int t = 0; t < tile_count() && rc == PSFS_OK; ++t) {
+        plan->tile = t;
+        for (int w = 0; w < 2 && rc == PSFS_OK; ++w) rc = enqueue_fuse(plan, lmap, post, occ, s);
+        if (rc) break;
+        const int reps = 5;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && rc == PSFS_OK; ++r) rc = enqueue_fuse(plan, lmap, post, occ, s);
+        hipEventRecord(e1, s);
+        if (rc) break;
+        e = hipEventSynchronize(e1);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipEventSynchronize"); break; }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) {
+        plan->tile = keep;
+        return rc;
+    }
+    plan->tile = best;
+    {
+        std::lock_guard<std::mutex> lock(tune_cache_mutex());
+        auto m = read_tune_cache(path);
+        m[key] = best;
+        write_tune_cache(path, m);
+    }
+    if (best_tile) *best_tile = best;
+    return PSFS_OK;
+    PSFS_GUARD_END
 }
 
 }  // extern "C"

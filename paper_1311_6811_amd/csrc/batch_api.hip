@@ -281,14 +281,6 @@ int run_eager(psfs_batch *b, void *ws, hipStream_t s)
 
 // ------------------------------------------------------------- tuning cache
 
-std::string cache_path()
-{
-    const char *p = std::getenv("PSFS_AUTOTUNE_CACHE");
-    if (p && *p) return p;
-    const char *home = std::getenv("HOME");
-    return std::string(home && *home ? home : "/tmp") + "/.cache/psfs/autotune.json";
-}
-
 std::string cache_key(const psfs_batch *b)
 {
     // FNV-1a over the shape signature
@@ -314,48 +306,6 @@ std::string cache_key(const psfs_batch *b)
     return buf;
 }
 
-std::mutex g_cache_mu;
-
-std::map<std::string, int> read_cache(const std::string &path)
-{
-    std::map<std::string, int> m;
-    std::ifstream in(path);
-    if (!in) return m;
-    std::stringstream ss;
-    ss << in.rdbuf();
-    const std::string s = ss.str();
-    size_t pos = 0;
-    while ((pos = s.find('"', pos)) != std::string::npos) {
-        const size_t end = s.find('"', pos + 1);
-        if (end == std::string::npos) break;
-        const std::string key = s.substr(pos + 1, end - pos - 1);
-        const size_t colon = s.find(':', end);
-        if (colon == std::string::npos) break;
-        m[key] = std::atoi(s.c_str() + colon + 1);
-        pos = s.find_first_of(",}", colon);
-        if (pos == std::string::npos) break;
-    }
-    return m;
-}
-
-void write_cache(const std::string &path, const std::map<std::string, int> &m)
-{
-    const size_t slash = path.find_last_of('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        for (size_t i = 1; i <= dir.size(); ++i)
-            if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
-    }
-    const std::string tmp = path + ".tmp";
-    {
-        std::ofstream out(tmp);
-        out << "{\n";
-        size_t i = 0;
-        for (const auto &kv : m) out << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
-        out << "}\n";
-    }
-    std::rename(tmp.c_str(), path.c_str());
-}
 
 }  // namespace
 
@@ -511,10 +461,10 @@ int psfs_batch_tune(psfs_batch *b, void *workspace_dev, size_t workspace_bytes_,
     int rc = check_run_args(b, workspace_dev, workspace_bytes_);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const std::string key = cache_key(b), path = cache_path();
+    const std::string key = cache_key(b), path = tune_cache_path();
     if (!force) {
-        std::lock_guard<std::mutex> lock(g_cache_mu);
-        const auto m = read_cache(path);
+        std::lock_guard<std::mutex> lock(tune_cache_mutex());
+        const auto m = read_tune_cache(path);
         const auto it = m.find(key);
         if (it != m.end() && it->second >= 0 && it->second < tile_count()) {
             if ((rc = psfs_batch_set_tile(b, it->second))) return rc;
@@ -549,10 +499,10 @@ int psfs_batch_tune(psfs_batch *b, void *workspace_dev, size_t workspace_bytes_,
     if (rc) return rc;
     if ((rc = psfs_batch_set_tile(b, best))) return rc;
     {
-        std::lock_guard<std::mutex> lock(g_cache_mu);
-        auto m = read_cache(path);
+        std::lock_guard<std::mutex> lock(tune_cache_mutex());
+        auto m = read_tune_cache(path);
         m[key] = best;
-        write_cache(path, m);
+        write_tune_cache(path, m);
     }
     if (best_tile) *best_tile = best;
     return PSFS_OK;

@@ -128,11 +128,27 @@ __device__ __forceinline__ int adjoint_exponent(float grad_loss, float inv_count
     return 19 - e;
 }
 
-// 1/c in FP64: hardware reciprocal and two Newton steps (about 1 ulp).
+// Projection rows of view v at an FP64 voxel column (X, Y), from the camera
+// matrix widened on the host (kernel arguments: scalar operands of the FMAs).
+__device__ __forceinline__ Proj64 proj64_view(const DiffArgs &a, int v, double X, double Y)
+{
+    const double *P = a.Pd[v];
+    Proj64 p;
+    p.ax = fma(P[0], X, fma(P[1], Y, P[3]));
+    p.bx = fma(P[4], X, fma(P[5], Y, P[7]));
+    p.cx = fma(P[8], X, fma(P[9], Y, P[11]));
+    p.pz0 = P[2];
+    p.pz1 = P[6];
+    p.pz2 = P[10];
+    return p;
+}
+
+// 1/c in FP64: the hardware reciprocal (relative error ~5e-8 on this GPU)
+// refined by one Newton step (~2e-15; a projected coordinate of ~1000 px is
+// then placed to ~1e-12 px).
 __device__ __forceinline__ double rcp64(double c)
 {
-    double r = __builtin_amdgcn_rcp(c);
-    r = fma(r, fma(-c, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(c);
     return fma(r, fma(-c, r, 1.0), r);
 }
 
@@ -181,7 +197,7 @@ __device__ __forceinline__ void compute_boxes(const DiffArgs &a, const Coords &q
         const double X = static_cast<double>(a.ox) + static_cast<double>(a.h) * ((corner & 1 ? q.bi + kBX - 1 : q.bi) + 0.5);
         const double Y = static_cast<double>(a.oy) + static_cast<double>(a.h) * ((corner & 2 ? q.bj + kBY - 1 : q.bj) + 0.5);
         const double Z = static_cast<double>(a.oz) + static_cast<double>(a.h) * ((corner & 4 ? q.kb + 4 * KZ - 1 : q.kb) + 0.5);
-        const Proj64 p = proj64_column(g, X, Y);
+        const Proj64 p = proj64_view(a, v, X, Y);
         const double c = fma(p.pz2, Z, p.cx);
         double ok = c > 0.0 ? 1.0 : 0.0;
         const double u = fma(p.pz0, Z, p.ax) / c, w = fma(p.pz1, Z, p.bx) / c;
@@ -230,14 +246,16 @@ __device__ __forceinline__ void box_rc(int e, int w, float inv_w, int &r, int &c
 }
 
 // Copies a view's map over the box into LDS; pixels outside the image read as
-// 0. All loads of a lane are issued before its LDS stores.
-__device__ __forceinline__ void stage_box(float *lds, const PixBox &b, const float *map, int W, int H)
+// 0. All loads of a lane are issued before its LDS stores. NP passes of the
+// workgroup cover boxes of up to NP * kBlock pixels.
+template <int NP>
+__device__ __forceinline__ void stage_box_n(float *lds, const PixBox &b, const float *map, int W, int H)
 {
     const int area = b.w * b.h;
     const float inv_w = 1.0f / static_cast<float>(b.w);
-    float vals[kStageIters];
+    float vals[NP];
 #pragma unroll
-    for (int t = 0; t < kStageIters; ++t) {
+    for (int t = 0; t < NP; ++t) {
         const int e = static_cast<int>(threadIdx.x) + t * kBlock;
         vals[t] = 0.0f;
         if (e < area) {
@@ -248,10 +266,23 @@ __device__ __forceinline__ void stage_box(float *lds, const PixBox &b, const flo
         }
     }
 #pragma unroll
-    for (int t = 0; t < kStageIters; ++t) {
+    for (int t = 0; t < NP; ++t) {
         const int e = static_cast<int>(threadIdx.x) + t * kBlock;
         if (e < area) lds[e] = vals[t];
     }
+}
+
+// stage_box_n with as few passes as the (workgroup-uniform) box needs: most
+// boxes of the 8x8-column workgroups hold under 1024 pixels.
+__device__ __forceinline__ void stage_box(float *lds, const PixBox &b, const float *map, int W, int H)
+{
+    const int area = b.w * b.h;
+    if (area <= 4 * kBlock)
+        stage_box_n<4>(lds, b, map, W, H);
+    else if (area <= 8 * kBlock)
+        stage_box_n<8>(lds, b, map, W, H);
+    else
+        stage_box_n<kStageIters>(lds, b, map, W, H);
 }
 
 __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
@@ -270,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
     for (int v = 0; v < a.n; ++v) {
         const ViewGeom &g = a.view[v];
         const float *map = a.lmap + g.map_off;
-        const Proj64 p = proj64_column(g, Xd, Yd);
+        const Proj64 p = proj64_view(a, v, Xd, Yd);
         const PixBox box = read_box(boxes, v);
         if (box.ok) {
             __syncthreads();                // the previous view's reads are done
@@ -385,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
         const ViewGeom &g = a.view[v];
         const float *map = a.lmap + g.map_off;
         unsigned long long *adj = reinterpret_cast<unsigned long long *>(a.adj) + g.map_off;
-        const Proj64 p = proj64_column(g, Xd, Yd);
+        const Proj64 p = proj64_view(a, v, Xd, Yd);
         PixBox box{0, 0, 0, 0, 0};
         if (block_any) box = read_box(boxes, v);
         if (box.ok) {

@@ -3,6 +3,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "psfs_internal.h"
 
@@ -16,6 +19,14 @@ bool finite_all(const float *v, int n);
 int check_device();
 int64_t padded_pixels(int width, int height);
 size_t align256(size_t x);
+
+// Autotuner cache (tune_cache.hip): $PSFS_AUTOTUNE_CACHE, else
+// $HOME/.cache/psfs/autotune.json; callers hold tune_cache_mutex() around
+// a read-modify-write.
+std::string tune_cache_path();
+std::mutex &tune_cache_mutex();
+std::map<std::string, int> read_tune_cache(const std::string &path);
+void write_tune_cache(const std::string &path, const std::map<std::string, int> &m);
 
 }  // namespace host
 }  // namespace psfs

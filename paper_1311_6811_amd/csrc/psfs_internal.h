@@ -98,6 +98,7 @@ struct PipeArgs {
 // geometry per view with the raw camera matrix).
 struct DiffArgs {
     ViewGeom view[kMaxViews];
+    double Pd[kMaxViews][12];           // each view's camera matrix widened to FP64 (the FP64 projection's operands)
     const float *lmap;                  // log(2*SLM) maps
     float *adj;                         // adjoint maps dLoss/dlog(2*SLM), int64 fixed point, same element layout
     const uint8_t *labels;              // [nz][ny][nx] 0/1

@@ -63,6 +63,10 @@ int main(void)
     CALL(psfs_reconstruct(p, imgs, (float *)fk, NULL, fk, 16, NULL));
     CALL(psfs_reconstruct_static(p, imgs, (float *)fk, NULL, NULL));
     CALL(psfs_reconstruct_static(NULL, imgs, (float *)fk, NULL, NULL));
+    CALL(psfs_tune(p, imgs, fk, 16, NULL, 0, NULL));
+    CALL(psfs_tune(NULL, imgs, fk, 16, NULL, 1, NULL));
+    CALL((int)psfs_tune_workspace_bytes(p));
+    CALL(psfs_get_tile(p));
     CALL(psfs_pipeline_step(p, imgs, (float *)fk, (const float *)fk, (float *)fk, NULL, NULL));
     CALL(psfs_pipeline_step(p, NULL, NULL, NULL, NULL, (uint8_t *)fk, NULL));
     CALL(psfs_threshold(NULL, -3, 0.5f, NULL, NULL));

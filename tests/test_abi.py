@@ -469,3 +469,25 @@ def test_reconstruct_static_validation_without_device(lib):
     assert lib.psfs_reconstruct_static(h, one, C.c_void_p(0x300000), None, None) == -2     # beyond the static array
     assert "static scratch" in lib.psfs_last_error().decode()
     lib.psfs_plan_destroy(h)
+
+
+def test_plan_tuner_validation_without_device(lib):
+    h = _plan(lib)
+    one = L.ptr_array([0x100000])
+    best = C.c_int32(-5)
+    assert lib.psfs_tune(None, one, None, 0, None, 0, C.byref(best)) == -1
+    assert lib.psfs_tune(h, one, None, 0, None, 0, C.byref(best)) == -3          # nothing set
+    assert lib.psfs_tune_workspace_bytes(h) == 0
+    cams = (L.psfs_camera * 1)(_cam(8, 6))
+    assert lib.psfs_set_cameras(h, 1, cams) == 0
+    assert lib.psfs_set_background(h, 0, C.c_void_p(0x100000), C.c_void_p(0x100000)) == 0
+    g = psfs.make_grid(4, 5, 6, (0, 0, 0), 0.1)
+    assert lib.psfs_set_grid(h, C.byref(g)) == 0
+    need = lib.psfs_tune_workspace_bytes(h)
+    assert need >= 3 * 256                                          # maps, posterior, occupancy regions
+    assert lib.psfs_tune(h, one, C.c_void_p(0x200000), need - 1, None, 0, C.byref(best)) == -4
+    assert lib.psfs_tune(h, one, C.c_void_p(0x200080), need, None, 0, C.byref(best)) == -4    # not 256-aligned
+    assert best.value == -5
+    assert lib.psfs_get_tile(h) >= 0 and lib.psfs_get_tile(None) == -1
+    assert lib.psfs_set_tile(h, 3) == 0 and lib.psfs_get_tile(h) == 3
+    lib.psfs_plan_destroy(h)

@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "paper_1311_6811_amd", "_build")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
 HOST_ASAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
-HOST_SOURCES = ("api.hip", "batch_api.hip")
+HOST_SOURCES = ("api.hip", "batch_api.hip", "tune_cache.hip")
 
 
 def test_host_code_under_asan(tmp_path):
