@@ -73,6 +73,8 @@ class Plan:
         h = C.c_void_p()
         L.check(L.lib().psfs_plan_create(C.byref(h)))
         self._h = h
+        # held by the object: module globals may be gone when it is collected at exit
+        self._destroy = L.lib().psfs_plan_destroy
         self._keep = {}
         self.cams = []
         self.grid = None
@@ -85,7 +87,7 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            L.lib().psfs_plan_destroy(h)
+            self._destroy(h)
             self._h = None
 
     @property
@@ -547,6 +549,7 @@ class Batch:
         h = C.c_void_p()
         L.check(L.lib().psfs_batch_create(C.byref(h), C.byref(self._params), len(frames), arr))
         self._h, self._keep, self.frames = h, keep, list(frames)
+        self._destroy = L.lib().psfs_batch_destroy
         self.workspace = torch.empty(max(int(L.lib().psfs_batch_workspace_bytes(h)), 256), dtype=torch.uint8,
                                      device="cuda")
 
@@ -579,7 +582,7 @@ class Batch:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            L.lib().psfs_batch_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def run(self) -> None:

@@ -95,22 +95,6 @@ __device__ __forceinline__ float dpp(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
 }
 
-// Sum over the 64 lanes, the same in every lane, in a fixed order: butterflies
-// within each 16-lane row (quad_perm xor 1, xor 2, row rotations by 4 and 8),
-// then the four row sums.
-__device__ __forceinline__ float wave_total(float v)
-{
-    v += dpp<0xb1>(v);
-    v += dpp<0x4e>(v);
-    v += dpp<0x124>(v);
-    v += dpp<0x128>(v);
-    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
-    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
-    return (r0 + r1) + (r2 + r3);
-}
-
 // Exponent E of the adjoint fixed point (see the file comment); 0 when G is
 // 0 or not finite (every term is then 0 or the input invalid).
 // Two's-complement int32 as the uint64 addend of a signed int64 sum.
@@ -159,10 +143,12 @@ struct Tap4 {
     float u, v, rc;
 };
 
-__device__ __forceinline__ bool project64(const Proj64 &p, double Zd, Tap4 &t)
+// Projection of a voxel centre known to lie in front of the camera (depth
+// c > 0): a voxel of a workgroup whose pixel box is valid, since the depth is
+// affine in the position and positive at every corner of the voxel box.
+__device__ __forceinline__ void project64_front(const Proj64 &p, double Zd, Tap4 &t)
 {
     const double c = fma(p.pz2, Zd, p.cx);
-    if (!(c > 0.0)) return false;
     const double r = rcp64(c);
     const double u = fma(p.pz0, Zd, p.ax) * r;
     const double w = fma(p.pz1, Zd, p.bx) * r;
@@ -173,6 +159,13 @@ __device__ __forceinline__ bool project64(const Proj64 &p, double Zd, Tap4 &t)
     t.u = static_cast<float>(u);
     t.v = static_cast<float>(w);
     t.rc = static_cast<float>(r);
+}
+
+// The same for any voxel centre: false when it is not in front.
+__device__ __forceinline__ bool project64(const Proj64 &p, double Zd, Tap4 &t)
+{
+    if (!(fma(p.pz2, Zd, p.cx) > 0.0)) return false;
+    project64_front(p, Zd, t);
     return true;
 }
 
@@ -307,19 +300,31 @@ __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
             __syncthreads();                // the previous view's reads are done
             stage_box(lmap_box, box, map, g.W, g.H);
             __syncthreads();
-        }
+            // box element of tap (x0, y0): (y0 - box.y0) w + (x0 - box.x0),
+            // exact in FP64 (integers far below 2^53)
+            const double wd = static_cast<double>(box.w);
+            const double od = static_cast<double>(box.y0) * wd + static_cast<double>(box.x0);
+            const int emax = box.w * box.h - box.w - 2;
+            // every voxel centre of the workgroup is in front of the camera and
+            // has both taps in the box (taps outside the image read the 0s the
+            // staging wrote there); the clamp only keeps the reads in the box
 #pragma unroll
-        for (int kk = 0; kk < kFwdKZ; ++kk) {
-            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
-            Tap4 t;
-            if (!project64(p, Zd, t)) continue;
-            const int lx = static_cast<int>(t.x0) - box.x0, ly = static_cast<int>(t.y0) - box.y0;
-            if (box.ok && t.x0 >= box.x0 && t.y0 >= box.y0 && lx + 1 < box.w && ly + 1 < box.h) {
-                const float *s = lmap_box + ly * box.w + lx;
+            for (int kk = 0; kk < kFwdKZ; ++kk) {
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                Tap4 t;
+                project64_front(p, Zd, t);
+                const int e = min(max(static_cast<int>(fma(t.y0, wd, t.x0 - od)), 0), emax);
+                const float *s = lmap_box + e;
                 const float top = fmaf(t.fx, s[1] - s[0], s[0]);
                 const float bot = fmaf(t.fx, s[box.w + 1] - s[box.w], s[box.w]);
                 L[kk] += fmaf(t.fy, bot - top, top);
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < kFwdKZ; ++kk) {
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                Tap4 t;
+                if (!project64(p, Zd, t)) continue;
                 L[kk] += bilinear_sample(map, g.W, g.H, t.x0, t.y0, t.fx, t.fy);
             }
         }
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256) void zero_kernel(float *p, int64_t n4)
 
 __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
 {
-    __shared__ float lmap_box[kBoxCap];
+    __shared__ __align__(16) float lmap_box[kBoxCap];
     __shared__ int adj_box[kBoxCap];
     __shared__ float cam[kWaves][kMaxViews * 12];
     __shared__ PixBox boxes[kMaxViews];
@@ -426,46 +431,70 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
             __syncthreads();
         }
         float su = 0.0f, suz = 0.0f, sv = 0.0f, svz = 0.0f, sc = 0.0f, scz = 0.0f;
+        if (box.ok) {
+            const double wd = static_cast<double>(box.w);
+            const double od = static_cast<double>(box.y0) * wd + static_cast<double>(box.x0);
+            const int emax = box.w * box.h - box.w - 2;
+            // as in the forward kernel: no per-voxel depth or range tests. A
+            // voxel whose taps all fall outside the image reads four 0s, adds
+            // 0 to the camera sums and scatters only into box pixels outside
+            // the image, which the flush skips: the same as skipping it.
 #pragma unroll
-        for (int kk = 0; kk < kBwdKZ; ++kk) {
-            if (gv[kk] == 0.0f) continue;
-            const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
-            Tap4 t;
-            if (!project64(p, Zd, t)) continue;
-            if (!(t.x0 >= -1.0 && t.x0 < g.W && t.y0 >= -1.0 && t.y0 < g.H)) continue;
-            const int ix = static_cast<int>(t.x0), iy = static_cast<int>(t.y0);
-            const bool xin0 = ix >= 0, xin1 = ix + 1 < g.W, yin0 = iy >= 0, yin1 = iy + 1 < g.H;
-            const float fx = t.fx, fy = t.fy, gk = gv[kk];
-            const int q00 = static_cast<int>(rintf(gk * (1.0f - fx) * (1.0f - fy) * qscale));
-            const int q10 = static_cast<int>(rintf(gk * fx * (1.0f - fy) * qscale));
-            const int q01 = static_cast<int>(rintf(gk * (1.0f - fx) * fy * qscale));
-            const int q11 = static_cast<int>(rintf(gk * fx * fy * qscale));
-            float l00, l10, l01, l11;
-            const int lx = ix - box.x0, ly = iy - box.y0;
-            if (box.ok && lx >= 0 && ly >= 0 && lx + 1 < box.w && ly + 1 < box.h) {
-                // out-of-image taps of the box hold 0 and are never flushed
-                const int e = ly * box.w + lx;
-                l00 = lmap_box[e]; l10 = lmap_box[e + 1]; l01 = lmap_box[e + box.w]; l11 = lmap_box[e + box.w + 1];
+            for (int kk = 0; kk < kBwdKZ; ++kk) {
+                if (gv[kk] == 0.0f) continue;
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                Tap4 t;
+                project64_front(p, Zd, t);
+                const float fx = t.fx, fy = t.fy, gk = gv[kk];
+                const int q00 = static_cast<int>(rintf(gk * (1.0f - fx) * (1.0f - fy) * qscale));
+                const int q10 = static_cast<int>(rintf(gk * fx * (1.0f - fy) * qscale));
+                const int q01 = static_cast<int>(rintf(gk * (1.0f - fx) * fy * qscale));
+                const int q11 = static_cast<int>(rintf(gk * fx * fy * qscale));
+                const int e = min(max(static_cast<int>(fma(t.y0, wd, t.x0 - od)), 0), emax);
+                const float l00 = lmap_box[e], l10 = lmap_box[e + 1], l01 = lmap_box[e + box.w], l11 = lmap_box[e + box.w + 1];
                 atomicAdd(&adj_box[e], q00);
                 atomicAdd(&adj_box[e + 1], q10);
                 atomicAdd(&adj_box[e + box.w], q01);
                 atomicAdd(&adj_box[e + box.w + 1], q11);
-            } else {
+                const float dldu = (1.0f - fy) * (l10 - l00) + fy * (l11 - l01);
+                const float dldv = (1.0f - fx) * (l01 - l00) + fx * (l11 - l10);
+                const float gu = gk * dldu * t.rc, gw = gk * dldv * t.rc;
+                const float gc = -(gu * t.u + gw * t.v);
+                const float Z = static_cast<float>(Zd);
+                su += gu; suz = fmaf(gu, Z, suz);
+                sv += gw; svz = fmaf(gw, Z, svz);
+                sc += gc; scz = fmaf(gc, Z, scz);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < kBwdKZ; ++kk) {
+                if (gv[kk] == 0.0f) continue;
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                Tap4 t;
+                if (!project64(p, Zd, t)) continue;
+                if (!(t.x0 >= -1.0 && t.x0 < g.W && t.y0 >= -1.0 && t.y0 < g.H)) continue;
+                const int ix = static_cast<int>(t.x0), iy = static_cast<int>(t.y0);
+                const bool xin0 = ix >= 0, xin1 = ix + 1 < g.W, yin0 = iy >= 0, yin1 = iy + 1 < g.H;
+                const float fx = t.fx, fy = t.fy, gk = gv[kk];
+                const int q00 = static_cast<int>(rintf(gk * (1.0f - fx) * (1.0f - fy) * qscale));
+                const int q10 = static_cast<int>(rintf(gk * fx * (1.0f - fy) * qscale));
+                const int q01 = static_cast<int>(rintf(gk * (1.0f - fx) * fy * qscale));
+                const int q11 = static_cast<int>(rintf(gk * fx * fy * qscale));
                 const int64_t base = static_cast<int64_t>(iy) * g.W + ix;
-                l00 = l10 = l01 = l11 = 0.0f;
+                float l00 = 0.0f, l10 = 0.0f, l01 = 0.0f, l11 = 0.0f;
                 if (xin0 && yin0) { l00 = map[base]; atomicAdd(adj + base, widen(q00)); }
                 if (xin1 && yin0) { l10 = map[base + 1]; atomicAdd(adj + base + 1, widen(q10)); }
                 if (xin0 && yin1) { l01 = map[base + g.W]; atomicAdd(adj + base + g.W, widen(q01)); }
                 if (xin1 && yin1) { l11 = map[base + g.W + 1]; atomicAdd(adj + base + g.W + 1, widen(q11)); }
+                const float dldu = (1.0f - fy) * (l10 - l00) + fy * (l11 - l01);
+                const float dldv = (1.0f - fx) * (l01 - l00) + fx * (l11 - l10);
+                const float gu = gk * dldu * t.rc, gw = gk * dldv * t.rc;
+                const float gc = -(gu * t.u + gw * t.v);
+                const float Z = static_cast<float>(Zd);
+                su += gu; suz = fmaf(gu, Z, suz);
+                sv += gw; svz = fmaf(gw, Z, svz);
+                sc += gc; scz = fmaf(gc, Z, scz);
             }
-            const float dldu = (1.0f - fy) * (l10 - l00) + fy * (l11 - l01);
-            const float dldv = (1.0f - fx) * (l01 - l00) + fx * (l11 - l10);
-            const float gu = gk * dldu * t.rc, gw = gk * dldv * t.rc;
-            const float gc = -(gu * t.u + gw * t.v);
-            const float Z = static_cast<float>(Zd);
-            su += gu; suz = fmaf(gu, Z, suz);
-            sv += gw; svz = fmaf(gw, Z, svz);
-            sc += gc; scz = fmaf(gc, Z, scz);
         }
         if (box.ok) {
             __syncthreads();                // every scatter into the box is done
@@ -483,11 +512,27 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
         // dLoss/dP row r = sum over the lane's voxels of g_r * (X, Y, Z, 1)
         if (block_any) {
             const float vals[12] = {X * su, Y * su, suz, su, X * sv, Y * sv, svz, sv, X * sc, Y * sc, scz, sc};
+            // Wave sums of the 12 entries through LDS, in a fixed order: the
+            // wave writes its 12 x 64 values, lane 4e + m adds lanes
+            // 16m .. 16m+15 of entry e, then a quad butterfly. The staged box
+            // is free here (every wave has passed the view's scatter barrier,
+            // and the next view stages after a barrier): each wave uses its
+            // own 768 floats of it.
+            float *red = lmap_box + wave * (12 * 64);
 #pragma unroll
-            for (int e = 0; e < 12; ++e) {
-                const float r = wave_total(vals[e]);
-                if (lane == 0) cam[wave][v * 12 + e] = r;
+            for (int e = 0; e < 12; ++e) red[e * 64 + lane] = vals[e];
+            wave_lds_sync();
+            float s = 0.0f;
+            if (lane < 48) {
+                const f32x4 *src = reinterpret_cast<const f32x4 *>(red + (lane >> 2) * 64 + (lane & 3) * 16);
+                const f32x4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+                s = (((r0.x + r0.y) + (r0.z + r0.w)) + ((r1.x + r1.y) + (r1.z + r1.w))) +
+                    (((r2.x + r2.y) + (r2.z + r2.w)) + ((r3.x + r3.y) + (r3.z + r3.w)));
             }
+            s += dpp<0xb1>(s);
+            s += dpp<0x4e>(s);
+            if (lane < 48 && (lane & 3) == 0) cam[wave][v * 12 + (lane >> 2)] = s;
+            wave_lds_sync();
         } else if (lane < 12) {
             cam[wave][v * 12 + lane] = 0.0f;
         }
