@@ -736,7 +736,8 @@ def measure_diff(torch, psfs, S, T, args, nslots=4):
 
 def measure_batch(torch, psfs, S, args, nframes=64):
     """The 64-frame uneven batch (grid edge in {64,96,128,192}, 4..12 views,
-    three image sizes) as two persistent launches replayed from a HIP graph."""
+    three image sizes): a chain of launches (each frame's likelihood beside the
+    previous frame's fusion) replayed from a HIP graph."""
     from concurrent.futures import ThreadPoolExecutor
     t0 = time.time()
     with ThreadPoolExecutor(8) as ex:

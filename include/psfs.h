@@ -432,12 +432,13 @@ typedef struct psfs_frame {
 
 typedef struct psfs_batch psfs_batch;  /* opaque */
 
-/* Plans a batch of nframes (1..65536) frames of uneven shapes processed by two
- * persistent launches (likelihood maps of every view of every frame, then
- * fusion of every frame, frames in decreasing voxels x views order, whose
- * workgroups pull voxel bricks from device counters, one contiguous slice of
- * bricks per XCD first). The launches are captured
- * into a HIP graph on the first run and replayed afterwards. Every frame's
+/* Plans a batch of nframes (1..65536) frames of uneven shapes, taken in
+ * decreasing voxels x views order and processed by a chain of nframes + 1
+ * launches: launch i computes the likelihood maps of frame i (Eq. 1-2) beside
+ * the fusion of frame i-1 (Eq. 3-9, threshold of Sec. 2.2.2), as the
+ * frame-sequence step does for one rig (two launches per step for the
+ * 128-lane tile). The launches read the frames from a device descriptor table
+ * and are captured into a HIP graph on the first run and replayed afterwards. Every frame's
  * result is bit-identical to psfs_reconstruct of that frame alone (same
  * params). Uses params.sampling (nearest, or the bilinear posterior).
  * Allocates a device descriptor table and a pinned host staging copy on the
@@ -450,7 +451,7 @@ size_t psfs_batch_workspace_bytes(const psfs_batch *batch);
  * the workspace pointer or the tile changes). On the null stream, or on a
  * stream the caller is capturing, the kernels are launched directly. Runs of
  * one batch must be ordered (one stream, or synchronised by the caller); they
- * share the workspace, which holds the likelihood maps and the work counters. Must
+ * share the workspace, which holds the likelihood maps of every frame. Must
  * run on the device the batch was created on (PSFS_E_DEVICE otherwise). */
 int psfs_batch_run(psfs_batch *batch, void *workspace_dev, size_t workspace_bytes, void *stream);
 /* Replaces the frames' pointers, camera matrices and grid placement (origin,

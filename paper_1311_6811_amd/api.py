@@ -539,8 +539,9 @@ class BatchFrame:
 
 
 class Batch:
-    """Many frames of uneven shape in two persistent launches replayed from a
-    HIP graph (see psfs_batch_* in psfs.h)."""
+    """Many frames of uneven shape in a chain of launches (each frame's
+    likelihood beside the previous frame's fusion) replayed from a HIP graph
+    (see psfs_batch_* in psfs.h)."""
 
     def __init__(self, frames: Sequence[BatchFrame], prior=0.5, log_u=LOG_U_DEFAULT, threshold=0.5,
                  sampling: int = L.NEAREST):

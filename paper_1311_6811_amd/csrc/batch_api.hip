@@ -34,9 +34,9 @@ struct psfs_batch {
     std::vector<const float *> means, vars;
     std::vector<BatchView> views;           // device table image (cost order)
     std::vector<BatchFrame> frames;
-    int64_t nchunks = 0, nbricks = 0, map_floats = 0;
-    int nstages = 0;                        // frame groups of the staged launches
-    int64_t stage_chunk[kBatchMaxStages + 1] = {}, stage_brick[kBatchMaxStages + 1] = {};
+    std::vector<int64_t> slm_per_view;      // per table frame: likelihood workgroups per view
+    std::vector<int64_t> fuse_tiles;        // per table frame: fusion bricks of the current tile
+    int64_t map_floats = 0;
     void *dtable = nullptr;
     void *staging = nullptr;                // pinned host image of dtable
     size_t dtable_bytes = 0;
@@ -98,15 +98,17 @@ void take_frames(psfs_batch *b, int nframes, const psfs_frame *frames)
     }
 }
 
-// Builds the descriptor table for the current frames and tile.
+// Builds the descriptor table (and the per-frame launch sizes) for the
+// current frames and tile.
 void build_table(psfs_batch *b)
 {
     const int nf = static_cast<int>(b->user.size());
     const bool nearest = b->params.sampling == PSFS_NEAREST;
     b->views.clear();
     b->frames.clear();
-    int64_t map_off = 0, chunk = 0, brick = 0;
-    const int64_t cp = batch_chunk_pixels();
+    b->slm_per_view.clear();
+    b->fuse_tiles.clear();
+    int64_t map_off = 0;
     for (int oi = 0; oi < nf; ++oi) {
         const int f = b->order[oi];
         const psfs_frame &u = b->user[f];
@@ -114,10 +116,9 @@ void build_table(psfs_batch *b)
         fr.grid = GridDesc{u.grid.nx, u.grid.ny, u.grid.nz, u.grid.origin[0], u.grid.origin[1], u.grid.origin[2], u.grid.voxel};
         fr.n = u.n;
         fr.view0 = static_cast<int32_t>(b->views.size());
-        fr.brick0 = brick;
         fr.post = u.posterior_dev;
         fr.occ = u.occ_dev;
-        brick += batch_bricks(u.grid.nx, u.grid.ny, u.grid.nz, b->tile);
+        int64_t max_np = 0;
         for (int k = 0; k < u.n; ++k) {
             const int ci = b->cam0[f] + k;
             const psfs_camera &c = b->cams[ci];
@@ -136,50 +137,21 @@ void build_table(psfs_batch *b)
             v.mean = b->means[ci];
             v.var = b->vars[ci];
             v.npix = static_cast<int64_t>(c.width) * c.height;
-            v.chunk0 = chunk;
-            chunk += (v.npix + cp - 1) / cp;
+            max_np = std::max(max_np, v.npix);
             map_off += padded_pixels(c.width, c.height);
             b->views.push_back(v);
         }
         b->frames.push_back(fr);
+        b->slm_per_view.push_back(batch_slm_blocks_per_view(max_np));
+        b->fuse_tiles.push_back(batch_bricks(u.grid.nx, u.grid.ny, u.grid.nz, b->tile));
     }
-    b->nchunks = chunk;
-    b->nbricks = brick;
     b->map_floats = map_off;
-    // Frame groups of the staged launches: consecutive frames of the table
-    // with about equal shares of the combined cost (voxel-views plus 4.4 per
-    // pixel: the measured ratio of likelihood time per pixel to fusion time
-    // per voxel-view), so that each launch's likelihood and fusion halves are
-    // of similar length.
-    b->nstages = std::min(kBatchMaxStages, nf);
-    std::vector<double> cum(nf + 1, 0.0);
-    for (int oi = 0; oi < nf; ++oi) {
-        const psfs_frame &u = b->user[b->order[oi]];
-        double px = 0.0;
-        for (int k = 0; k < u.n; ++k) px += static_cast<double>(b->cams[b->cam0[b->order[oi]] + k].width) *
-                                           b->cams[b->cam0[b->order[oi]] + k].height;
-        const double vv = static_cast<double>(u.grid.nx) * u.grid.ny * u.grid.nz * u.n;
-        cum[oi + 1] = cum[oi] + vv + 4.4 * px;
-    }
-    int f0 = 0;
-    for (int g = 0; g <= b->nstages; ++g) {
-        int fe = nf;
-        if (g < b->nstages) {
-            const double target = cum[nf] * g / b->nstages;
-            fe = f0;
-            while (fe < nf && cum[fe] < target) ++fe;
-        }
-        // first chunk / brick of frame fe (or the totals past the last frame)
-        b->stage_brick[g] = fe < nf ? b->frames[fe].brick0 : b->nbricks;
-        b->stage_chunk[g] = fe < nf ? b->views[b->frames[fe].view0].chunk0 : b->nchunks;
-        f0 = fe;
-    }
     b->dirty = true;
 }
 
 size_t workspace_bytes(const psfs_batch *b)
 {
-    return align256(static_cast<size_t>(b->map_floats) * sizeof(float)) + kBatchCounterBytes;
+    return std::max<size_t>(256, align256(static_cast<size_t>(b->map_floats) * sizeof(float)));
 }
 
 void drop_graph(psfs_batch *b)
@@ -199,32 +171,11 @@ BatchArgs make_args(const psfs_batch *b, void *ws)
     a.frames = reinterpret_cast<const BatchFrame *>(static_cast<const char *>(b->dtable) +
                                                      align256(b->views.size() * sizeof(BatchView)));
     a.lmap = static_cast<float *>(ws);
-    a.counters = reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) +
-                                                        align256(static_cast<size_t>(b->map_floats) * sizeof(float)));
-    a.nchunks = b->nchunks;
-    a.nbricks = b->nbricks;
-    a.nviews = static_cast<int32_t>(b->views.size());
-    a.nframes = static_cast<int32_t>(b->frames.size());
     a.k0 = static_cast<float>(-1.5 * std::log(2.0 * M_PI) - static_cast<double>(b->params.log_u));
     const double pr = b->params.prior;
     a.L0 = static_cast<float>(std::log(pr / (1.0 - pr)));
     a.tau = b->params.threshold;
-    a.nstages = b->nstages;
-    for (int g = 0; g <= kBatchMaxStages; ++g) {
-        a.stage_chunk[g] = b->stage_chunk[g];
-        a.stage_brick[g] = b->stage_brick[g];
-    }
     return a;
-}
-
-int grids(const psfs_batch *b, int &slm_grid, int &fuse_grid)
-{
-    const int64_t slm_items = (b->nchunks + 3) / 4, fuse_items = (b->nbricks + 3) / 4;
-    const int64_t slm_cap = static_cast<int64_t>(b->cus) * 8;
-    const int64_t fuse_cap = static_cast<int64_t>(b->cus) * batch_fuse_occupancy(b->tile, b->params.sampling);
-    slm_grid = static_cast<int>(std::max<int64_t>(1, std::min(slm_items, slm_cap)));
-    fuse_grid = static_cast<int>(std::max<int64_t>(1, std::min(fuse_items, fuse_cap)));
-    return PSFS_OK;
 }
 
 int upload_table(psfs_batch *b, hipStream_t s)
@@ -260,16 +211,20 @@ int check_run_args(psfs_batch *b, void *ws, size_t bytes)
     return PSFS_OK;
 }
 
-// The launches of one run: staged (tiles of 256 lanes) or likelihood then fusion.
+// The launches of one run: table frame i's likelihood beside frame i-1's
+// fusion, i = 0 .. nframes (one launch per step for tiles of 256 lanes, two
+// for the 128-lane tile).
 hipError_t enqueue_batch(const psfs_batch *b, void *ws, hipStream_t s)
 {
-    if (batch_staged_tile(b->tile)) {
-        const int grid = std::max(1, b->cus * batch_stage_occupancy(b->tile, b->params.sampling));
-        return launch_batch_staged(make_args(b, ws), b->tile, b->params.sampling, grid, s);
+    const BatchArgs a = make_args(b, ws);
+    const int nf = static_cast<int>(b->frames.size());
+    for (int i = 0; i <= nf; ++i) {
+        const int fl = i < nf ? i : -1, ff = i - 1;
+        hipError_t e = launch_batch_step(a, b->tile, b->params.sampling, fl, fl >= 0 ? b->slm_per_view[fl] : 0,
+                                         fl >= 0 ? b->frames[fl].n : 0, ff, ff >= 0 ? b->fuse_tiles[ff] : 0, s);
+        if (e != hipSuccess) return e;
     }
-    int sg, fg;
-    grids(b, sg, fg);
-    return launch_batch(make_args(b, ws), b->tile, b->params.sampling, sg, fg, s);
+    return hipSuccess;
 }
 
 int run_eager(psfs_batch *b, void *ws, hipStream_t s)
@@ -301,7 +256,7 @@ std::string cache_key(const psfs_batch *b)
         }
     }
     char buf[128];
-    std::snprintf(buf, sizeof(buf), "gfx950/%dcu/s%d/%016llx", b->cus, b->params.sampling,
+    std::snprintf(buf, sizeof(buf), "gfx950/%dcu/chain/s%d/%016llx", b->cus, b->params.sampling,
                   static_cast<unsigned long long>(h));
     return buf;
 }

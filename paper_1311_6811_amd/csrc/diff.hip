@@ -576,62 +576,123 @@ __device__ __forceinline__ void camera_gradient(const ChainArgs &a, int v)
     }
 }
 
+// dLoss/dmu_c and dLoss/dvar_c of one pixel from its adjoint A (the
+// reciprocal of each variance once, refined to about half an ulp).
 __device__ __forceinline__ void chain_pixel(float A, float i0, float i1, float i2, const float m[3], const float v[3],
                                             float k0, float gm[3], float gvv[3])
 {
-    const float d = pixel_d(i0, i1, i2, m[0], m[1], m[2], v[0], v[1], v[2], k0);
-    const float s = -A * sigmoidf_stable(d);        // dLoss/dd
     const float I[3] = {i0, i1, i2};
+    float t[3], rv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float t = (I[c] - m[c]) / v[c];
-        gm[c] = s * t;
-        gvv[c] = s * (0.5f * t * t - 0.5f / v[c]);
+        rv[c] = recip(v[c]);
+        t[c] = (I[c] - m[c]) * rv[c];
     }
+    const float q = fmaf(I[0] - m[0], t[0], fmaf(I[1] - m[1], t[1], (I[2] - m[2]) * t[2]));   // sum d_c^2 / v_c
+    const float half_logdet = (0.5f * kLn2) * (__builtin_amdgcn_logf(v[0] * v[1]) + __builtin_amdgcn_logf(v[2]));
+    const float d = (k0 - half_logdet) - 0.5f * q;
+    const float s = -A * sigmoid_fast(d);           // dLoss/dd
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        gm[c] = s * t[c];
+        gvv[c] = s * (0.5f * t[c] * t[c] - 0.5f * rv[c]);
+    }
+}
+
+typedef long long i64x2 __attribute__((ext_vector_type(2)));
+
+// The chain for the pixels [p0, p0 + 256) of one view (p0 a multiple of 4,
+// all inside the view): each load instruction of the wave reads one
+// contiguous span, the lanes regroup the inputs per pixel quad through LDS
+// (as the likelihood pass does) and regroup the gradients back so that each
+// store instruction writes one contiguous span.
+__device__ __forceinline__ void chain_wave(const ChainView &cv, const long long *adj, double unit, float k0,
+                                           int64_t p0, SlmStage &st)
+{
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const f32x4 *mp = reinterpret_cast<const f32x4 *>(cv.mean + 3 * p0);
+    const f32x4 *vp = reinterpret_cast<const f32x4 *>(cv.var + 3 * p0);
+    const uint32_t *ip = reinterpret_cast<const uint32_t *>(cv.img + 3 * p0);
+    const i64x2 *ap = reinterpret_cast<const i64x2 *>(adj + p0 + 4 * lane);
+    f32x4 m[3], v[3];
+    uint32_t w[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        m[r] = __builtin_nontemporal_load(mp + lane + 64 * r);
+        v[r] = __builtin_nontemporal_load(vp + lane + 64 * r);
+        w[r] = __builtin_nontemporal_load(ip + lane + 64 * r);
+    }
+    const i64x2 a01 = __builtin_nontemporal_load(ap), a23 = __builtin_nontemporal_load(ap + 1);
+    const float A[4] = {static_cast<float>(static_cast<double>(a01.x) * unit), static_cast<float>(static_cast<double>(a01.y) * unit),
+                        static_cast<float>(static_cast<double>(a23.x) * unit), static_cast<float>(static_cast<double>(a23.y) * unit)};
+    f32x4 qm[3], qv[3];
+    uint32_t qw[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        st.f[lane + 64 * r] = m[r];
+        st.w[lane + 64 * r] = w[r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        qm[r] = st.f[3 * lane + r];
+        qw[r] = st.w[3 * lane + r];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) st.f[lane + 64 * r] = v[r];
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) qv[r] = st.f[3 * lane + r];
+    wave_lds_sync();
+    float mm[12], vv[12], gm[12], gvv[12];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        mm[4 * r] = qm[r].x; mm[4 * r + 1] = qm[r].y; mm[4 * r + 2] = qm[r].z; mm[4 * r + 3] = qm[r].w;
+        vv[4 * r] = qv[r].x; vv[4 * r + 1] = qv[r].y; vv[4 * r + 2] = qv[r].z; vv[4 * r + 3] = qv[r].w;
+    }
+#pragma unroll
+    for (int px = 0; px < 4; ++px) {
+        const int b = 3 * px;
+        chain_pixel(A[px], byte_of(qw[b / 4], b % 4), byte_of(qw[(b + 1) / 4], (b + 1) % 4),
+                    byte_of(qw[(b + 2) / 4], (b + 2) % 4), mm + b, vv + b, k0, gm + b, gvv + b);
+    }
+    f32x4 *gmo = reinterpret_cast<f32x4 *>(cv.gmean + 3 * p0);
+    f32x4 *gvo = reinterpret_cast<f32x4 *>(cv.gvar + 3 * p0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) st.f[3 * lane + r] = f32x4{gm[4 * r], gm[4 * r + 1], gm[4 * r + 2], gm[4 * r + 3]};
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gmo[lane + 64 * r] = st.f[lane + 64 * r];
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) st.f[3 * lane + r] = f32x4{gvv[4 * r], gvv[4 * r + 1], gvv[4 * r + 2], gvv[4 * r + 3]};
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gvo[lane + 64 * r] = st.f[lane + 64 * r];
 }
 
 __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
 {
+    __shared__ SlmStage st[4];
     if (blockIdx.x == 0) camera_gradient(a, static_cast<int>(blockIdx.y));
     const ChainView cv = a.view[blockIdx.y];
-    const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
-    if (p0 >= cv.npix) return;
-    const long long *Aq = reinterpret_cast<const long long *>(a.adj) + cv.map_off + p0;
+    const int wave = static_cast<int>(threadIdx.x >> 6);
+    const int64_t pw = (static_cast<int64_t>(blockIdx.x) * 4 + wave) * 256;   // the wave's first pixel
+    if (pw >= cv.npix) return;
+    const long long *adj = reinterpret_cast<const long long *>(a.adj) + cv.map_off;
     const double unit = ldexp(1.0, -adjoint_exponent(*a.grad_loss, a.inv_count));
-    float A[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) A[t] = p0 + t < cv.npix ? static_cast<float>(static_cast<double>(Aq[t]) * unit) : 0.0f;
-    if (p0 + 4 <= cv.npix) {
-        const uint32_t *iw = reinterpret_cast<const uint32_t *>(cv.img + 3 * p0);
-        const uint32_t w[3] = {iw[0], iw[1], iw[2]};
-        const f32x4 *mp = reinterpret_cast<const f32x4 *>(cv.mean + 3 * p0);
-        const f32x4 *vp = reinterpret_cast<const f32x4 *>(cv.var + 3 * p0);
-        float m[12], v[12], gm[12], gvv[12];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const f32x4 mm = mp[r], vv = vp[r];
-            m[4 * r] = mm.x; m[4 * r + 1] = mm.y; m[4 * r + 2] = mm.z; m[4 * r + 3] = mm.w;
-            v[4 * r] = vv.x; v[4 * r + 1] = vv.y; v[4 * r + 2] = vv.z; v[4 * r + 3] = vv.w;
-        }
-#pragma unroll
-        for (int px = 0; px < 4; ++px) {
-            const int b = 3 * px;
-            chain_pixel(A[px], byte_of(w[b / 4], b % 4), byte_of(w[(b + 1) / 4], (b + 1) % 4),
-                        byte_of(w[(b + 2) / 4], (b + 2) % 4), m + b, v + b, a.k0, gm + b, gvv + b);
-        }
-        f32x4 *gmo = reinterpret_cast<f32x4 *>(cv.gmean + 3 * p0);
-        f32x4 *gvo = reinterpret_cast<f32x4 *>(cv.gvar + 3 * p0);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            gmo[r] = f32x4{gm[4 * r], gm[4 * r + 1], gm[4 * r + 2], gm[4 * r + 3]};
-            gvo[r] = f32x4{gvv[4 * r], gvv[4 * r + 1], gvv[4 * r + 2], gvv[4 * r + 3]};
-        }
-    } else {
-        for (int64_t p = p0; p < cv.npix; ++p) {
-            const uint8_t *I = cv.img + 3 * p;
-            chain_pixel(A[p - p0], I[0], I[1], I[2], cv.mean + 3 * p, cv.var + 3 * p, a.k0, cv.gmean + 3 * p,
-                        cv.gvar + 3 * p);
-        }
+    if (pw + 256 <= cv.npix) {
+        chain_wave(cv, adj, unit, a.k0, pw, st[wave]);
+        return;
+    }
+    // the view's last, partial span: lane by lane
+    const int64_t p0 = pw + 4 * static_cast<int64_t>(threadIdx.x & 63);
+    if (p0 >= cv.npix) return;
+    for (int64_t p = p0; p < cv.npix && p < p0 + 4; ++p) {
+        const uint8_t *I = cv.img + 3 * p;
+        const float A = static_cast<float>(static_cast<double>(adj[p]) * unit);
+        chain_pixel(A, I[0], I[1], I[2], cv.mean + 3 * p, cv.var + 3 * p, a.k0, cv.gmean + 3 * p, cv.gvar + 3 * p);
     }
 }
 

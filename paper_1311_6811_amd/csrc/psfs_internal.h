@@ -143,36 +143,21 @@ struct BatchView {
     const float *mean;
     const float *var;
     int64_t npix;
-    int64_t chunk0;                     // first likelihood-map chunk of this view
 };
 
 struct BatchFrame {
     GridDesc grid;
     int32_t n, view0;                   // views [view0, view0 + n) of the table
-    int64_t brick0;                     // first fusion brick of this frame
     float *post;
     uint8_t *occ;                       // nullable
 };
 
-constexpr int kBatchMaxStages = 4;      // frame groups of a staged batch
-
 struct BatchArgs {
     const BatchView *views;
-    const BatchFrame *frames;           // decreasing cost order
-    float *lmap;
-    unsigned long long *counters;       // work counters (a kBatchCounterBytes region), reset by the first launch
-    int64_t nchunks, nbricks;
-    int32_t nviews, nframes;
+    const BatchFrame *frames;           // table order (decreasing cost)
+    float *lmap;                        // map arena
     float k0, L0, tau;
-    // Staged launches: the frames (in table order) form nstages groups; group
-    // g owns likelihood chunks [stage_chunk[g], stage_chunk[g+1]) and fusion
-    // bricks [stage_brick[g], stage_brick[g+1]). Launch s runs group s's
-    // likelihood beside group s-1's fusion.
-    int32_t nstages;
-    int64_t stage_chunk[kBatchMaxStages + 1];
-    int64_t stage_brick[kBatchMaxStages + 1];
 };
-constexpr size_t kBatchCounterBytes = 512;
 
 // Smoothing, threshold and surface extraction of one posterior grid.
 struct SurfArgs {
@@ -235,15 +220,16 @@ int64_t diff_bwd_blocks(int nx, int ny, int nz);
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s);
 hipError_t launch_diff_backward(const DiffArgs &a, const ChainArgs &c, int64_t map_floats, int64_t max_npix,
                                 float *gP, hipStream_t s);
-int64_t batch_chunk_pixels();
+// Batch: likelihood workgroups per view for views of up to max_npix pixels;
+// fusion bricks of a frame for a tile; whether a tile runs the pipelined
+// launches (256 lanes) or separate ones; one step of the launch chain (the
+// likelihood of table frame fl beside the fusion of table frame ff, either
+// of them -1 for none).
+int64_t batch_slm_blocks_per_view(int64_t max_npix);
 int64_t batch_bricks(int nx, int ny, int nz, int tile);
-int batch_fuse_occupancy(int tile, int sampling);
-hipError_t launch_batch(const BatchArgs &a, int tile, int sampling, int slm_grid, int fuse_grid, hipStream_t s);
-// Staged variant (tiles of 256 lanes): a counter reset, then nstages + 1
-// launches of batch_stage_kernel with `grid` workgroups each.
-bool batch_staged_tile(int tile);
-int batch_stage_occupancy(int tile, int sampling);
-hipError_t launch_batch_staged(const BatchArgs &a, int tile, int sampling, int grid, hipStream_t s);
+bool batch_pipelined_tile(int tile);
+hipError_t launch_batch_step(const BatchArgs &a, int tile, int sampling, int fl, int64_t slm_per_view, int nviews_l,
+                             int ff, int64_t fuse_tiles, hipStream_t s);
 hipError_t launch_threshold(const float *post, int64_t n, float tau, uint8_t *occ, hipStream_t s);
 int64_t surface_blocks(int64_t nvox);
 hipError_t launch_colour(const ColourArgs &a, hipStream_t s);

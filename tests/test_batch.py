@@ -1,4 +1,4 @@
-"""Batched persistent pass over frames of uneven shape, replayed from a HIP graph.
+"""Batched pass over frames of uneven shape (a chain of pipelined launches), replayed from a HIP graph.
 
 Every frame of a batch must be bit-identical to the same frame reconstructed
 alone (same per-pixel and per-column code, fixed view order), and match the
@@ -179,9 +179,9 @@ def test_batch_with_the_largest_grid():
 
 
 def test_every_tile_keeps_the_bits(mixed):
-    """Each tile (the staged launches for 256-lane tiles, likelihood then
-    fusion for the 128-lane one) gives every frame the bits of the frame
-    alone."""
+    """Each tile (one launch per chain step for 256-lane tiles, likelihood
+    then fusion launches for the 128-lane one) gives every frame the bits of
+    the frame alone."""
     frames, bfs = mixed
     refs = []
     for fr, bf in zip(frames[:7], bfs[:7]):
