@@ -128,6 +128,30 @@ def test_every_output_bitwise_reproducible(scene):
     assert all(np.array_equal(x, y) for x, y in zip(a[3], b[3]))
 
 
+def test_loss_of_each_forward_on_one_workspace(scene):
+    """Forwards with alternating label sets on one plan and one workspace:
+    each loss equals that label set's loss from a fresh plan and workspace,
+    bit for bit (no partial of an earlier forward leaks into a later sum)."""
+    fr, cams, labels = scene
+    rng = np.random.default_rng(5)
+    other = (rng.random(labels.shape) < 0.3).astype(np.uint8)
+    fresh = [run_gpu(fr, cams, lab)[1] for lab in (labels, other)]
+    assert fresh[0] != fresh[1]
+    ims, mus, vs = upload(fr)
+    plan = psfs.Plan(cams, fr.grid, sampling=psfs.BILINEAR)
+    plan.set_backgrounds(mus, vs)
+    labs = [torch.from_numpy(labels).cuda(), torch.from_numpy(other).cuda()]
+    ws = plan.new_diff_workspace()
+    logits = torch.empty((fr.grid.nz, fr.grid.ny, fr.grid.nx), dtype=torch.float32, device="cuda")
+    losses = [torch.empty((), dtype=torch.float32, device="cuda") for _ in range(6)]
+    for i in range(6):
+        plan.diff_forward(ims, labs[i % 2], None, logits, losses[i], ws)
+    torch.cuda.synchronize()
+    got = [float(x) for x in losses]
+    say(f"  losses {got}")
+    assert got == [fresh[i % 2] for i in range(6)]
+
+
 def test_empty_loss_region_gives_zero():
     fr = S.config_frame(0, 0)
     labels = S.gt_occupancy(fr.grid, fr.body)
