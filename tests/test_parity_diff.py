@@ -118,6 +118,31 @@ def test_small_scene_ragged_and_edge_views():
     check_grads(gm, gv, gP, ref, "ragged")
 
 
+def test_boxes_too_large_or_behind_a_camera_take_the_direct_path():
+    """Workgroups whose pixel box exceeds the LDS cap (a close camera with a
+    long focal length) or has a corner behind the camera (a camera inside
+    the grid) sample the maps directly; logits and gradients still follow
+    the oracle."""
+    rng = np.random.default_rng(23)
+    cams = [S.look_at_camera((1.6, 0.4, 0.3), 900.0, 320, 240),            # boxes of ~10^5 pixels
+            S.look_at_camera((0.35, 0.25, 0.12), 150.0, 200, 150, target=(-1.0, -0.5, 0.0)),   # inside the grid
+            S.look_at_camera((-3.0, 1.5, 1.0), 280.0, 180, 140)]           # an ordinary view
+    grid = S.Grid(40, 36, 30, np.array([-1.0, -0.9, -0.75], np.float32), np.float32(0.05))
+    body = S.make_body(rng)
+    fr = S.render_frame(20, 1, cams, grid, body, (20, 1))
+    labels = S.gt_occupancy(grid, body)
+    logits, loss, gm, gv, gP = run_gpu(fr, cams, labels)
+    l2s = [O.log2slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
+    L = O.bilinear_logits(cams, grid, l2s)
+    err = float(np.max(np.abs(logits - L)))
+    say(f"  logits max error {err:.2e}")
+    assert err <= LOGIT_TOL
+    want = O.bce_loss(L, labels)
+    assert abs(loss - want) <= LOSS_RTOL * abs(want)
+    ref = O.grad(cams, grid, fr.images, fr.mean, fr.var, labels)
+    check_grads(gm, gv, gP, ref, "direct path")
+
+
 def test_every_output_bitwise_reproducible(scene):
     # fixed-order reductions and fixed-point (integer) adjoint accumulation
     fr, cams, labels = scene
