@@ -433,7 +433,7 @@ typedef struct psfs_frame {
 typedef struct psfs_batch psfs_batch;  /* opaque */
 
 /* Plans a batch of nframes (1..65536) frames of uneven shapes, taken in
- * decreasing voxels x views order and processed by a chain of nframes + 1
+ * an order that pairs similar likelihood and fusion costs, and processed by a chain of nframes + 1
  * launches: launch i computes the likelihood maps of frame i (Eq. 1-2) beside
  * the fusion of frame i-1 (Eq. 3-9, threshold of Sec. 2.2.2), as the
  * frame-sequence step does for one rig (two launches per step for the

@@ -1,4 +1,4 @@
-// Host side of the batched pass: frame validation, decreasing-cost ordering,
+// Host side of the batched pass: frame validation, the launch-chain order,
 // the device descriptor table, HIP-graph capture/replay and the tile
 // autotuner with its on-disk cache.
 #include <algorithm>
@@ -27,7 +27,7 @@ struct psfs_batch {
     int cus = 0;
     int tile = 0;
     std::vector<psfs_frame> user;           // caller's frame structs (pointers to their arrays not kept)
-    std::vector<int> order;                 // order[i] = user frame placed i-th (decreasing cost)
+    std::vector<int> order;                 // order[i] = user frame placed i-th in the chain (chain_order)
     std::vector<psfs_camera> cams;          // all cameras, user frame order
     std::vector<int> cam0;                  // first camera of each user frame
     std::vector<const uint8_t *> imgs;
@@ -80,6 +80,49 @@ bool same_signature(const psfs_frame &a, const psfs_frame &b)
     for (int k = 0; k < a.n; ++k)
         if (a.cams[k].width != b.cams[k].width || a.cams[k].height != b.cams[k].height) return false;
     return true;
+}
+
+// Order of the frames in the launch chain (launch i runs frame i's likelihood
+// beside frame i-1's fusion). Costs in voxel-view units: fusion = voxels x
+// views, likelihood = 4.4 per pixel (the measured ratio of likelihood time per
+// pixel to fusion time per voxel-view). The chain starts with the cheapest
+// likelihood and each next frame is the unplaced one whose likelihood cost is
+// closest to the previous frame's fusion cost, so that the two halves of a
+// launch are of similar length (2.79 ms instead of 2.85 for the 64 uneven
+// frames against decreasing-cost order). Above kGreedyFrames frames (the
+// greedy pass is quadratic) the order is decreasing fusion cost.
+constexpr int kGreedyFrames = 4096;
+
+void chain_order(const psfs_frame *frames, int nframes, std::vector<int> &order)
+{
+    std::vector<double> fuse(nframes), lik(nframes);
+    for (int f = 0; f < nframes; ++f) {
+        fuse[f] = static_cast<double>(frames[f].grid.nx) * frames[f].grid.ny * frames[f].grid.nz * frames[f].n;
+        double px = 0.0;
+        for (int k = 0; k < frames[f].n; ++k) px += static_cast<double>(frames[f].cams[k].width) * frames[f].cams[k].height;
+        lik[f] = 4.4 * px;
+    }
+    order.resize(nframes);
+    std::iota(order.begin(), order.end(), 0);
+    if (nframes > kGreedyFrames) {
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return fuse[x] > fuse[y]; });
+        return;
+    }
+    std::vector<char> used(nframes, 0);
+    int cur = 0;
+    for (int f = 1; f < nframes; ++f)
+        if (lik[f] < lik[cur]) cur = f;
+    for (int i = 0; i < nframes; ++i) {
+        order[i] = cur;
+        used[cur] = 1;
+        int next = -1;
+        for (int f = 0; f < nframes; ++f) {
+            if (used[f]) continue;
+            if (next < 0 || std::fabs(lik[f] - fuse[cur]) < std::fabs(lik[next] - fuse[cur])) next = f;
+        }
+        if (next < 0) break;
+        cur = next;
+    }
 }
 
 // Copies the caller's frames (and the arrays they point to) into the batch.
@@ -290,12 +333,7 @@ int psfs_batch_create(psfs_batch **out, const psfs_params *params, int nframes, 
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e != hipSuccess) { delete b; return hip_fail(e, "device query"); }
     take_frames(b, nframes, frames);
-    b->order.resize(nframes);
-    std::iota(b->order.begin(), b->order.end(), 0);
-    std::vector<double> cost(nframes);
-    for (int f = 0; f < nframes; ++f)
-        cost[f] = static_cast<double>(frames[f].grid.nx) * frames[f].grid.ny * frames[f].grid.nz * frames[f].n;
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    chain_order(frames, nframes, b->order);
     b->tile = default_tile();
     build_table(b);
     b->dtable_bytes = align256(b->views.size() * sizeof(BatchView)) + align256(b->frames.size() * sizeof(BatchFrame));

@@ -154,7 +154,7 @@ struct BatchFrame {
 
 struct BatchArgs {
     const BatchView *views;
-    const BatchFrame *frames;           // table order (decreasing cost)
+    const BatchFrame *frames;           // table order = launch-chain order
     float *lmap;                        // map arena
     float k0, L0, tau;
 };
