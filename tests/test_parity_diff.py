@@ -177,6 +177,25 @@ def test_loss_of_each_forward_on_one_workspace(scene):
     assert got == [fresh[i % 2] for i in range(6)]
 
 
+def test_backward_twice_after_one_forward(scene):
+    """A second backward after the same forward (no forward in between to
+    clear the adjoint maps) gives the bits of the first."""
+    fr, cams, labels = scene
+    ims, mus, vs = upload(fr)
+    plan = psfs.Plan(cams, fr.grid, sampling=psfs.BILINEAR)
+    plan.set_backgrounds(mus, vs)
+    lab = torch.from_numpy(labels).cuda()
+    logits, loss, ws = plan.diff_forward(ims, lab)
+    gl = torch.ones((), dtype=torch.float32, device="cuda")
+    first = plan.diff_backward(ims, lab, logits, gl, ws)
+    first = [[g.clone() for g in first[0]], [g.clone() for g in first[1]], first[2].clone()]
+    second = plan.diff_backward(ims, lab, logits, gl, ws)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(first[0], second[0]))
+    assert all(torch.equal(a, b) for a, b in zip(first[1], second[1]))
+    assert torch.equal(first[2], second[2])
+
+
 def test_empty_loss_region_gives_zero():
     fr = S.config_frame(0, 0)
     labels = S.gt_occupancy(fr.grid, fr.body)
