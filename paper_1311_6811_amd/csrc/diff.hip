@@ -32,45 +32,15 @@ namespace {
 
 using namespace dev;
 
-// Backward workgroup = 8 x 8 voxel columns x (4 * KZ) slices; its 4 waves each
-// cover a 4 x 4 group of columns and 4 interleaved z-slices (lane l: column
-// (l & 3, (l >> 2) & 3), slice (l >> 4) + 4 * kk for kk < KZ). A wave is thus a
-// 4 x 4 x 4 voxel block in every instruction, so at most ~4 of its lanes lie on
-// one viewing ray of a horizontal camera: few lanes share a pixel, which keeps
-// same-address LDS atomics in the adjoint scatter rare. The forward, which has
-// no atomics, uses wider blocks (fwd_coords): a pixel box serves more voxels.
-constexpr int kBX = 8, kBY = 8;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kBwdKZ = 8;
 constexpr int kBoxCap = 4096;           // floats of one view's pixel box staged in LDS
 constexpr int kStageIters = kBoxCap / kBlock;
 
 struct Coords {
-    int i, j, kb, lz;                   // lane column, first slice of the workgroup, lane slice offset
+    int i, j, kb;                       // lane column, first slice of the workgroup
     int bi, bj;                         // first column of the workgroup
 };
-
-template <int KZ>
-__device__ __forceinline__ Coords block_coords(int nx, int ny, int nz)
-{
-    const int ntx = (nx + kBX - 1) / kBX, nty = (ny + kBY - 1) / kBY;
-    const int64_t ntile = static_cast<int64_t>(ntx) * nty;
-    const int64_t nb = ntile * ((nz + 4 * KZ - 1) / (4 * KZ));
-    const int64_t b = xcd_remap(blockIdx.x, nb);
-    const int64_t zc = b / ntile;
-    const int t = static_cast<int>(b - zc * ntile);
-    const int tyi = t / ntx, txi = t - tyi * ntx;
-    const int w = static_cast<int>(threadIdx.x >> 6), l = static_cast<int>(threadIdx.x & 63);
-    Coords c;
-    c.bi = txi * kBX;
-    c.bj = tyi * kBY;
-    c.i = c.bi + 4 * (w & 1) + (l & 3);
-    c.j = c.bj + 4 * (w >> 1) + ((l >> 2) & 3);
-    c.kb = static_cast<int>(zc) * 4 * KZ;
-    c.lz = l >> 4;
-    return c;
-}
 
 __device__ __forceinline__ bool in_region(const DiffArgs &a, int i, int j, int k)
 {
@@ -179,14 +149,19 @@ struct PixBox {
     int x0, y0, w, h, ok;
 };
 
-// Forward workgroup = 16 x 16 voxel columns x 8 slices, lane t the column
-// (t % 16, t / 16) and its 8 slices. Its views' pixel boxes hold ~0.7 pixels
-// per voxel at 128^3 x 8 views of 640x480, against ~0.9 for 8 x 8 x 16
-// blocks, and the per-view work (box, barriers, projection rows) is shared by
-// twice the voxels.
+// Workgroup of either pass = 16 x 16 voxel columns x kFZ slices, a lane one
+// column and its kFZ voxels. Its views' pixel boxes hold ~0.7 pixels per
+// voxel at 128^3 x 8 views of 640x480 (~0.9 for 8 x 8 x 16 or 8 x 8 x 32
+// blocks), and the per-view work (box, barriers, projection rows) is shared
+// by 2048 voxels. The forward's waves are 16 x 4 columns (lane t: column
+// (t % 16, t / 16)); the backward's are 8 x 8 columns (wave w, lane l: column
+// (8 (w & 1) + l % 8, 8 (w >> 1) + l / 8)), so that fewer of its lanes lie on
+// one viewing ray of a ring camera, where they would add into the same
+// pixels of the adjoint box (same-address LDS atomics).
 constexpr int kFX = 16, kFY = 16, kFZ = 8;
 
-__device__ __forceinline__ Coords fwd_coords(int nx, int ny, int nz)
+template <bool SQUARE_WAVES>
+__device__ __forceinline__ Coords block_coords(int nx, int ny, int nz)
 {
     const int ntx = (nx + kFX - 1) / kFX, nty = (ny + kFY - 1) / kFY;
     const int64_t ntile = static_cast<int64_t>(ntx) * nty;
@@ -195,13 +170,18 @@ __device__ __forceinline__ Coords fwd_coords(int nx, int ny, int nz)
     const int64_t zc = b / ntile;
     const int t = static_cast<int>(b - zc * ntile);
     const int tyi = t / ntx, txi = t - tyi * ntx;
+    const int w = static_cast<int>(threadIdx.x >> 6), l = static_cast<int>(threadIdx.x & 63);
     Coords c;
     c.bi = txi * kFX;
     c.bj = tyi * kFY;
-    c.i = c.bi + static_cast<int>(threadIdx.x % kFX);
-    c.j = c.bj + static_cast<int>(threadIdx.x / kFX);
+    if (SQUARE_WAVES) {
+        c.i = c.bi + 8 * (w & 1) + (l & 7);
+        c.j = c.bj + 8 * (w >> 1) + (l >> 3);
+    } else {
+        c.i = c.bi + static_cast<int>(threadIdx.x % kFX);
+        c.j = c.bj + static_cast<int>(threadIdx.x / kFX);
+    }
     c.kb = static_cast<int>(zc) * kFZ;
-    c.lz = 0;
     return c;
 }
 
@@ -308,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void diff_fwd_kernel(DiffArgs a)
 {
     __shared__ float lmap_box[kBoxCap];
     __shared__ PixBox boxes[kMaxViews];
-    const Coords q = fwd_coords(a.nx, a.ny, a.nz);
+    const Coords q = block_coords<false>(a.nx, a.ny, a.nz);
     compute_boxes<kFX, kFY, kFZ>(a, q, boxes);
     const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (q.i + 0.5);
     const double Yd = static_cast<double>(a.oy) + static_cast<double>(a.h) * (q.j + 0.5);
@@ -417,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
     __shared__ int adj_box[kBoxCap];
     __shared__ float cam[kWaves][kMaxViews * 12];
     __shared__ PixBox boxes[kMaxViews];
-    const Coords q = block_coords<kBwdKZ>(a.nx, a.ny, a.nz);
+    const Coords q = block_coords<true>(a.nx, a.ny, a.nz);
     const float X = a.ox + a.h * (static_cast<float>(q.i) + 0.5f);
     const float Y = a.oy + a.h * (static_cast<float>(q.j) + 0.5f);
     const double Xd = static_cast<double>(a.ox) + static_cast<double>(a.h) * (q.i + 0.5);
@@ -425,11 +405,11 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
     const float gl = *a.grad_loss;
     const float qscale = ldexpf(1.0f, adjoint_exponent(gl, a.inv_count));
 
-    float gv[kBwdKZ];
+    float gv[kFZ];
     bool any = false;
 #pragma unroll
-    for (int kk = 0; kk < kBwdKZ; ++kk) {
-        const int k = q.kb + q.lz + 4 * kk;
+    for (int kk = 0; kk < kFZ; ++kk) {
+        const int k = q.kb + kk;
         gv[kk] = 0.0f;
         if (q.i < a.nx && q.j < a.ny && k < a.nz && in_region(a, q.i, q.j, k)) {
             const int64_t idx = (static_cast<int64_t>(k) * a.ny + q.j) * a.nx + q.i;
@@ -439,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
     }
     // a workgroup with no voxel in the loss region contributes nothing
     const bool block_any = __syncthreads_or(any ? 1 : 0) != 0;
-    if (block_any) compute_boxes<kBX, kBY, 4 * kBwdKZ>(a, q, boxes);
+    if (block_any) compute_boxes<kFX, kFY, kFZ>(a, q, boxes);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
@@ -466,9 +446,9 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
             // 0 to the camera sums and scatters only into box pixels outside
             // the image, which the flush skips: the same as skipping it.
 #pragma unroll
-            for (int kk = 0; kk < kBwdKZ; ++kk) {
+            for (int kk = 0; kk < kFZ; ++kk) {
                 if (gv[kk] == 0.0f) continue;
-                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + kk + 0.5);
                 Tap4 t;
                 project64_front(p, Zd, t);
                 const float fx = t.fx, fy = t.fy, gk = gv[kk];
@@ -493,9 +473,9 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
             }
         } else {
 #pragma unroll
-            for (int kk = 0; kk < kBwdKZ; ++kk) {
+            for (int kk = 0; kk < kFZ; ++kk) {
                 if (gv[kk] == 0.0f) continue;
-                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + q.lz + 4 * kk + 0.5);
+                const double Zd = static_cast<double>(a.oz) + static_cast<double>(a.h) * (q.kb + kk + 0.5);
                 Tap4 t;
                 if (!project64(p, Zd, t)) continue;
                 if (!(t.x0 >= -1.0 && t.x0 < g.W && t.y0 >= -1.0 && t.y0 < g.H)) continue;
@@ -722,18 +702,13 @@ __global__ __launch_bounds__(256) void pixel_chain_kernel(ChainArgs a)
     }
 }
 
-int64_t nblocks(int nx, int ny, int nz, int kz)
-{
-    return static_cast<int64_t>((nx + kBX - 1) / kBX) * ((ny + kBY - 1) / kBY) * ((nz + 4 * kz - 1) / (4 * kz));
-}
-
 }  // namespace
 
 int64_t diff_fwd_blocks(int nx, int ny, int nz)
 {
     return static_cast<int64_t>((nx + kFX - 1) / kFX) * ((ny + kFY - 1) / kFY) * ((nz + kFZ - 1) / kFZ);
 }
-int64_t diff_bwd_blocks(int nx, int ny, int nz) { return nblocks(nx, ny, nz, kBwdKZ); }
+int64_t diff_bwd_blocks(int nx, int ny, int nz) { return diff_fwd_blocks(nx, ny, nz); }
 
 hipError_t launch_diff_forward(const DiffArgs &a, float *loss, hipStream_t s)
 {

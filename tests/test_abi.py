@@ -373,11 +373,10 @@ def test_diff_validation_without_device(lib):
         assert lib.psfs_set_background(h, k, fake, fake) == 0
     need = lib.psfs_diff_workspace_bytes(h)
     # two padded maps (2 x 128 floats), their int64 fixed-point adjoints, one
-    # FP64 partial per forward workgroup
-    # and 2 x 12 FP32 partials per backward workgroup (workgroups: 8 x 8 voxel
-    # columns x 16 slices forward, x 32 slices backward), each region 256-byte aligned
-    nbf = 5 * 1 * 1
-    nbb = 5 * 1 * 1
+    # FP64 partial per forward workgroup and 2 x 12 FP32 partials per backward
+    # workgroup (both: 16 x 16 voxel columns x 8 slices), each region 256-byte aligned
+    nbf = 3 * 1 * 2
+    nbb = 3 * 1 * 2
     want = 512 + 1024 + 256 * ((nbf * 8 + 255) // 256) + 256 * ((nbb * 24 * 4 + 255) // 256)
     assert need == want
     imgs = L.ptr_array([0x100000, 0x100000])
