@@ -677,6 +677,9 @@ def measure_particles(torch, psfs, S, T, args, n_particles=200):
     return res
 
 
+DIFF_ROUNDS = 5
+
+
 def measure_diff(torch, psfs, S, T, args, nslots=4):
     """Differentiable pass on the 128^3 x 8-view workload (bilinear sampling,
     BCE against the ellipsoid occupancy, cameras perturbed 1 %): forward alone
@@ -708,8 +711,10 @@ def measure_diff(torch, psfs, S, T, args, nslots=4):
             d["plan"].diff_backward(d["ims"], d["lab"], d["logits"], d["gl"], d["ws"], None, d["gm"], d["gv"], d["gP"])
         return f
 
-    t_f = T.calls([fwd(d) for d in slots])
-    t_fb = T.calls([fwdbwd(d) for d in slots])
+    # DIFF_ROUNDS passes over the slots per graph, so that the graph launch is
+    # not counted with each call
+    t_f = T.calls([fwd(d) for d in slots] * DIFF_ROUNDS)
+    t_fb = T.calls([fwdbwd(d) for d in slots] * DIFF_ROUNDS)
     ms_f, ms_fb = t_f["median"], t_fb["median"]
     print(f"[bench] differentiable: fwd {ms_f * 1e3:.2f} us, fwd+bwd {ms_fb * 1e3:.2f} us", file=sys.stderr, flush=True)
     fr = S.config_frame(4, 0)

@@ -420,6 +420,9 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
     // a workgroup with no voxel in the loss region contributes nothing
     const bool block_any = __syncthreads_or(any ? 1 : 0) != 0;
     if (block_any) compute_boxes<kFX, kFY, kFZ>(a, q, boxes);
+    // the adjoint box starts at zero once; each view's flush clears the
+    // entries it reads, and a view scatters only inside its own box
+    for (int e = threadIdx.x; e < kBoxCap; e += kBlock) adj_box[e] = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
@@ -433,7 +436,6 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
         if (box.ok) {
             __syncthreads();                // the previous view's flush is done
             stage_box(lmap_box, box, map, g.W, g.H);
-            for (int e = threadIdx.x; e < box.w * box.h; e += kBlock) adj_box[e] = 0;
             __syncthreads();
         }
         float su = 0.0f, suz = 0.0f, sv = 0.0f, svz = 0.0f, sc = 0.0f, scz = 0.0f;
@@ -511,6 +513,7 @@ __global__ __launch_bounds__(kBlock) void diff_bwd_kernel(DiffArgs a)
                 box_rc(e, box.w, inv_w, r, c);
                 const int x = box.x0 + c, y = box.y0 + r;
                 const int val = adj_box[e];
+                adj_box[e] = 0;
                 if (x >= 0 && x < g.W && y >= 0 && y < g.H && val != 0)
                     atomicAdd(adj + static_cast<int64_t>(y) * g.W + x, widen(val));
             }
@@ -723,7 +726,7 @@ hipError_t launch_diff_backward(const DiffArgs &a, const ChainArgs &c, int64_t m
 {
     if (map_floats > 0) {
         const int64_t n4 = map_floats / 4;
-        const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 4096);
+        const int64_t blocks = std::min<int64_t>((n4 + 1023) / 1024, 4096);
         hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a.adj, n4);
     }
     const int64_t nb = diff_bwd_blocks(a.nx, a.ny, a.nz);
