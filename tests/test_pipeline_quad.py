@@ -123,6 +123,25 @@ def test_quad_ragged_sequence_foreground_and_oracle():
     plan.set_foreground(None)
 
 
+def test_quad_cameras_inside_and_close_to_the_grid():
+    """Views whose pixel box cannot be staged: a camera inside the grid (block
+    corners behind it), a close camera with a long focal length (boxes larger
+    than the staging buffer) and a camera looking past the grid (boxes that
+    miss the image), beside an ordinary view, on a grid that is ragged for
+    every block shape: every frame bit-identical to the frame alone."""
+    say("four-frame sequence, cameras inside, close to and looking past the grid")
+    rng = np.random.default_rng(43)
+    cams = [S.look_at_camera((0.05, -0.1, 0.02), 300.0, 200, 150, target=(1.0, 0.3, 0.1)),
+            S.look_at_camera((1.4, 0.2, 0.3), 700.0, 640, 480),
+            S.look_at_camera((-4.0, 0.5, 1.5), 150.0, 320, 240, target=(-1.0, 3.5, 1.0)),
+            S.look_at_camera((3.5, -2.0, 1.0), 150.0, 320, 240)]
+    grid = S.Grid(50, 41, 27, np.array([-1.0, -0.82, -0.54], np.float32), np.float32(0.04))
+    frames = [S.render_frame(14, f, cams, grid, S.make_body(rng), (14, 0)) for f in range(4)]
+    plan, images = sequence(frames)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+
+
 def test_quad_zero_views_give_the_prior():
     say("four-frame step, no views")
     fr = S.config_frame(0, 0)
