@@ -100,6 +100,7 @@ hipError_t launch_pipe_s(const BatchArgs &a, int tile, int fl, int ff, const Pip
     case 3: return launch_pipe_t<8, 32, 2, S>(a, fl, ff, p, s);
     case 4: return launch_pipe_t<32, 8, 4, S>(a, fl, ff, p, s);
     case 5: return launch_pipe_t<16, 16, 4, S>(a, fl, ff, p, s);
+    case 6: return launch_pipe_t<16, 16, 8, S>(a, fl, ff, p, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -188,6 +188,245 @@ __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImage
     }
 }
 
+// ---- one-frame nearest fusion from pixel boxes staged in LDS ----------------
+// A workgroup of kSBThreads lanes fuses a kSBX x kSBY x kSBZ block of voxels
+// (lane t: column (t % 16, (t / 16) % 16), voxels kSBKZ (t / 256) ..
+// kSBKZ (t / 256) + kSBKZ - 1 of the block's slices). Per view, the voxel
+// centres of the block project into the hull of its 8 projected corner
+// centres (the depth is affine and positive at every corner, so on the block
+// the projection is continuous and maps the box into that hull); the pixel
+// box around the hull, widened by a bound on the FP32 rounding of the
+// per-voxel projection, holds every pixel a voxel-view of the block reads.
+// The boxes of all views are copied into one LDS arena in view order by
+// direct-to-LDS 4-byte buffer loads (one wave instruction per 64 consecutive
+// box entries; pixels outside the image read as 0), so that a workgroup waits
+// once for all its loads; the voxel-views then read LDS. Views whose box does
+// not fit in what is left of the arena, or whose corners are not clearly in
+// front of the camera, are gathered directly; views whose box misses the
+// image are skipped (every voxel-view of them adds 0). Same per-voxel
+// projection arithmetic, pixel rule and view order as fuse_column: the
+// posteriors are bit-identical.
+constexpr int kSBX = 16, kSBY = 16, kSBZ = 8;
+constexpr int kSBThreads = 512;
+constexpr int kSBKZ = kSBX * kSBY * kSBZ / kSBThreads;
+constexpr int kSArena = 8192;                       // staged floats per workgroup: 32 KB
+static_assert(kSBKZ * (kSBThreads / (kSBX * kSBY)) == kSBZ, "lanes cover the block");
+
+struct SBox {
+    int x0, y0, w, area;
+    int mode;                                       // 0: misses the image, 1: stageable, 2: direct gathers
+};
+
+// Voxel centre coordinate, as every fusion path computes it.
+__device__ __forceinline__ float voxel_centre(float o, float h, int i)
+{
+    return o + h * (static_cast<float>(i) + 0.5f);
+}
+
+// Pixel boxes of every view for the block with first voxel (i_lo, j_lo, k_lo)
+// (phantom voxels past the grid edge included, so that every lane's voxel
+// lies in the hull). Lanes 8v .. 8v+7 of the first two waves take the corners
+// of view v in FP64 from the FP32 centres the voxel lanes use; lane 8v writes
+// boxes[v]. The FP32 evaluation of floor's argument for a voxel (three
+// roundings in each of the numerator and the depth, a reciprocal of 1 ulp and
+// a product) is within 1.8e-7 (S_u + |u| S_c) / c + 1.8e-7 |u| of the exact
+// value, with S the sum of the absolute terms of a row: over the block S is
+// largest and c smallest at a corner. The box is widened by 2^-6 px plus five
+// times that bound.
+template <class Views>
+__device__ __forceinline__ void block_boxes(const Views &views, int n, const GridDesc &a, int i_lo, int j_lo,
+                                            int k_lo, SBox *boxes)
+{
+    const int t = static_cast<int>(threadIdx.x);
+    if (t >= 8 * kMaxViews) return;                 // whole waves: the shuffles need every lane
+    const int v = (t >> 3) < n ? (t >> 3) : 0;
+    const int corner = t & 7;
+    const ViewGeom &g = views(v);
+    const double X = voxel_centre(a.ox, a.h, i_lo + ((corner & 1) ? kSBX - 1 : 0));
+    const double Y = voxel_centre(a.oy, a.h, j_lo + ((corner & 2) ? kSBY - 1 : 0));
+    const double Z = voxel_centre(a.oz, a.h, k_lo + ((corner & 4) ? kSBZ - 1 : 0));
+    double row[3], sum[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double t0 = static_cast<double>(g.P[4 * q]) * X, t1 = static_cast<double>(g.P[4 * q + 1]) * Y;
+        const double t2 = static_cast<double>(g.P[4 * q + 2]) * Z, t3 = static_cast<double>(g.P[4 * q + 3]);
+        row[q] = (t0 + t1) + (t2 + t3);
+        sum[q] = (fabs(t0) + fabs(t1)) + (fabs(t2) + fabs(t3));
+    }
+    const double c = row[2];
+    // NaN fails every comparison below; the 2^20 limits keep the conversions exact
+    bool ok = c > 1e-4 * sum[2] && sum[2] < 1e30;
+    const double u = ok ? row[0] / c : 0.0, w = ok ? row[1] / c : 0.0;
+    ok = ok && fabs(u) < 1048576.0 && fabs(w) < 1048576.0;
+    double umin = u, umax = u, wmin = w, wmax = w, cmin = ok ? c : -1.0;
+    double su = sum[0], sw = sum[1], sc = sum[2], au = fabs(u), aw = fabs(w);
+#pragma unroll
+    for (int m = 1; m <= 4; m <<= 1) {
+        umin = fmin(umin, __shfl_xor(umin, m, 64));
+        umax = fmax(umax, __shfl_xor(umax, m, 64));
+        wmin = fmin(wmin, __shfl_xor(wmin, m, 64));
+        wmax = fmax(wmax, __shfl_xor(wmax, m, 64));
+        cmin = fmin(cmin, __shfl_xor(cmin, m, 64));
+        su = fmax(su, __shfl_xor(su, m, 64));
+        sw = fmax(sw, __shfl_xor(sw, m, 64));
+        sc = fmax(sc, __shfl_xor(sc, m, 64));
+        au = fmax(au, __shfl_xor(au, m, 64));
+        aw = fmax(aw, __shfl_xor(aw, m, 64));
+    }
+    if ((t >> 3) >= n || corner != 0) return;
+    SBox b{0, 0, 0, 0, 2};
+    if (cmin > 0.0) {
+        const double mu = 0.015625 + 9e-7 * ((su + au * sc) / cmin + au);
+        const double mw = 0.015625 + 9e-7 * ((sw + aw * sc) / cmin + aw);
+        if (mu < 0.25 && mw < 0.25) {
+            const int x0 = static_cast<int>(floor(umin - mu)), x1 = static_cast<int>(floor(umax + mu));
+            const int y0 = static_cast<int>(floor(wmin - mw)), y1 = static_cast<int>(floor(wmax + mw));
+            const int bw = x1 - x0 + 1, bh = y1 - y0 + 1;
+            if (x1 < 0 || x0 >= g.W || y1 < 0 || y0 >= g.H)
+                b.mode = 0;
+            else if (bw <= kSArena && bh <= kSArena && bw * bh <= kSArena)
+                b = SBox{x0, y0, bw, bw * bh, 1};
+        }
+    }
+    boxes[v] = b;
+}
+
+__device__ __forceinline__ SBox read_sbox(const SBox *boxes, int v)
+{
+    SBox b;
+    b.x0 = __builtin_amdgcn_readfirstlane(boxes[v].x0);
+    b.y0 = __builtin_amdgcn_readfirstlane(boxes[v].y0);
+    b.w = __builtin_amdgcn_readfirstlane(boxes[v].w);
+    b.area = __builtin_amdgcn_readfirstlane(boxes[v].area);
+    b.mode = __builtin_amdgcn_readfirstlane(boxes[v].mode);
+    return b;
+}
+
+template <class Views>
+__device__ __forceinline__ void fuse_block(const Views &views, int n, const float *lmap, const GridDesc &a,
+                                           uint32_t bi, uint32_t bj, uint32_t bk, float L0, float tau, float *post,
+                                           uint8_t *occ, float *arena, SBox *boxes)
+{
+    const int t = static_cast<int>(threadIdx.x);
+    const int wave = t >> 6, lane = t & 63;
+    const int i_lo = static_cast<int>(bi) * kSBX, j_lo = static_cast<int>(bj) * kSBY, k_lo = static_cast<int>(bk) * kSBZ;
+    const int i = i_lo + (t % kSBX), j = j_lo + (t / kSBX) % kSBY, k0 = k_lo + kSBKZ * (t / (kSBX * kSBY));
+    block_boxes(views, n, a, i_lo, j_lo, k_lo, boxes);
+    const float X = voxel_centre(a.ox, a.h, i), Y = voxel_centre(a.oy, a.h, j);
+    float Z[kSBKZ], L[kSBKZ];
+#pragma unroll
+    for (int kk = 0; kk < kSBKZ; ++kk) {
+        Z[kk] = voxel_centre(a.oz, a.h, k0 + kk);
+        L[kk] = L0;
+    }
+    __syncthreads();                                // boxes visible
+
+    // Stage every view's box that fits in what is left of the arena, in view
+    // order (each wave derives the same offsets); box entry e = r w + c is
+    // pixel (x0 + c, y0 + r); pixels outside the image get an offset past the
+    // end of the map, which loads 0.
+    int off = 0;
+    for (int v = 0; v < n; ++v) {
+        const SBox b = read_sbox(boxes, v);
+        if (b.mode != 1 || off + b.area > kSArena) continue;
+        const ViewGeom &g = views(v);
+        const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+        const __amdgpu_buffer_rsrc_t rs = map_rsrc(lmap + g.map_off, W * H * 4u);
+        const float inv_w = 1.0f / static_cast<float>(b.w);
+        for (int q = wave; q * 64 < b.area; q += kSBThreads / 64) {
+            const int e = q * 64 + lane;
+            if (e < b.area) {
+                // (e + 1/2) / w is at least 1/(2w) from an integer and e < 2^22: exact row
+                const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_w);
+                const int c = e - r * b.w;
+                const uint32_t x = static_cast<uint32_t>(b.x0 + c), y = static_cast<uint32_t>(b.y0 + r);
+                const uint32_t o = (x < W && y < H) ? (__umul24(y, W) + x) * 4u : 0xFFFFFFFFu;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(arena + off + q * 64),
+                                                         4, o, 0, 0, 0);
+            }
+        }
+        off += b.area;
+    }
+    __syncthreads();                                // every wave's loads have landed
+
+    off = 0;
+    for (int v = 0; v < n; ++v) {
+        const SBox b = read_sbox(boxes, v);
+        if (b.mode == 0) continue;
+        const ViewGeom &g = views(v);
+        const float ax = fmaf(g.P[0], X, fmaf(g.P[1], Y, g.P[3]));
+        const float bx = fmaf(g.P[4], X, fmaf(g.P[5], Y, g.P[7]));
+        const float cx = fmaf(g.P[8], X, fmaf(g.P[9], Y, g.P[11]));
+        if (b.mode == 1 && off + b.area <= kSArena) {
+            // box entry of pixel (x, y): (y - y0) w + (x - x0), exact in FP32
+            // (integers below 2^24); the clamp only keeps the reads in the box
+            const float *sb = arena + off;
+            const float wf = static_cast<float>(b.w);
+            const float od = static_cast<float>(b.y0) * wf + static_cast<float>(b.x0);
+            const float emax = static_cast<float>(b.area - 1);
+#pragma unroll
+            for (int kk = 0; kk < kSBKZ; ++kk) {
+                const float r = __builtin_amdgcn_rcpf(fmaf(g.P[10], Z[kk], cx));
+                const float x = floorf(fmaf(g.P[2], Z[kk], ax) * r);
+                const float y = floorf(fmaf(g.P[6], Z[kk], bx) * r);
+                const float ef = __builtin_amdgcn_fmed3f(fmaf(y, wf, x - od), 0.0f, emax);
+                L[kk] += sb[static_cast<int>(ef)];
+            }
+            off += b.area;
+        } else {
+            const uint32_t W = static_cast<uint32_t>(g.W), H = static_cast<uint32_t>(g.H);
+            const __amdgpu_buffer_rsrc_t rs = map_rsrc(lmap + g.map_off, W * H * 4u);
+            float val[kSBKZ];
+#pragma unroll
+            for (int kk = 0; kk < kSBKZ; ++kk) {
+                const float c = fmaf(g.P[10], Z[kk], cx);
+                const float r = __builtin_amdgcn_rcpf(c);
+                const int x = static_cast<int>(floorf(fmaf(g.P[2], Z[kk], ax) * r));
+                const int y = static_cast<int>(floorf(fmaf(g.P[6], Z[kk], bx) * r));
+                const bool ok = c > 0.0f && static_cast<uint32_t>(x) < W && static_cast<uint32_t>(y) < H;
+                val[kk] = map_load(rs, ok ? (__umul24(static_cast<uint32_t>(y), W) + static_cast<uint32_t>(x)) * 4u
+                                          : 0xFFFFFFFFu);
+            }
+#pragma unroll
+            for (int kk = 0; kk < kSBKZ; ++kk) L[kk] += val[kk];
+        }
+    }
+    if (i >= a.nx || j >= a.ny) return;
+    const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
+    int64_t idx = (static_cast<int64_t>(k0) * a.ny + j) * a.nx + i;
+#pragma unroll
+    for (int kk = 0; kk < kSBKZ; ++kk, idx += plane) {
+        if (k0 + kk < a.nz) {
+            const float p = sigmoid_fast(L[kk]);
+            post[idx] = p;
+            if (occ) occ[idx] = p > tau ? 1 : 0;
+        }
+    }
+}
+
+template <class T>
+__host__ __device__ int64_t block_count(const T &a)
+{
+    return static_cast<int64_t>((a.nx + kSBX - 1) / kSBX) * ((a.ny + kSBY - 1) / kSBY) * ((a.nz + kSBZ - 1) / kSBZ);
+}
+
+// One-frame nearest fusion, one voxel block per workgroup; the blocks of one
+// XCD form one contiguous octant-ordered range.
+__global__ __launch_bounds__(kSBThreads) void fuse_block_kernel(FuseArgs f)
+{
+    __shared__ float arena[kSArena];
+    __shared__ SBox boxes[kMaxViews];
+    const int64_t nb = block_count(f);
+    const uint32_t b = static_cast<uint32_t>(xcd_remap(blockIdx.x, nb));
+    const uint32_t nbx = static_cast<uint32_t>((f.nx + kSBX - 1) / kSBX), nby = static_cast<uint32_t>((f.ny + kSBY - 1) / kSBY);
+    const uint32_t nbz = static_cast<uint32_t>((f.nz + kSBZ - 1) / kSBZ);
+    uint32_t bi, bj, bk;
+    octant_tile(b, nbx, nby, nbz, bi, bj, bk);
+    const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};
+    fuse_block([&](int v) -> const ViewGeom & { return f.view[v]; }, f.n, f.lmap, gd, bi, bj, bk, f.L0, f.tau,
+               f.post, f.occ, arena, boxes);
+}
+
 __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)
 {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -195,9 +434,21 @@ __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64
         occ[i] = post[i] > tau ? 1 : 0;
 }
 
+// Tile kBlockTile is the kSBX x kSBY x kSBZ voxel block: the one-frame
+// nearest paths fuse it from pixel boxes staged in LDS (fuse_block_kernel),
+// bilinear sampling with 16 x 16 columns of 8 voxels.
 constexpr TileCfg kTiles[] = {
-    {8, 32, 4}, {8, 32, 8}, {8, 16, 4}, {8, 32, 2}, {32, 8, 4}, {16, 16, 4},
+    {8, 32, 4}, {8, 32, 8}, {8, 16, 4}, {8, 32, 2}, {32, 8, 4}, {16, 16, 4}, {kSBX, kSBY, kSBZ},
 };
+constexpr int kBlockTile = 6;
+
+hipError_t launch_fuse_block(const FuseArgs &a, hipStream_t s)
+{
+    const int64_t nb = block_count(a);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(fuse_block_kernel, dim3(static_cast<unsigned>(nb)), dim3(kSBThreads), 0, s, a);
+    return hipGetLastError();
+}
 
 template <int TX, int TY, int KZ, int S>
 hipError_t launch_pipe_t(const SlmArgs &sa, const FuseArgs &fa, int64_t max_npix, hipStream_t s)
@@ -219,7 +470,17 @@ hipError_t launch_pipe_t(const SlmArgs &sa, const FuseArgs &fa, int64_t max_npix
 template <int S>
 hipError_t launch_pipe_s(const SlmArgs &sa, const FuseArgs &fa, int tile, int64_t max_npix, hipStream_t s)
 {
+    if (S == PSFS_NEAREST && tile == kBlockTile) {
+        // the block kernel's LDS would cut the likelihood rounds' occupancy in
+        // a shared launch: likelihood rounds alone, then the block fusion
+        FuseArgs none = fa;
+        none.post = nullptr;
+        hipError_t e = launch_pipe_t<8, 32, 4, S>(sa, none, max_npix, s);
+        if (e == hipSuccess && fa.post) e = launch_fuse_block(fa, s);
+        return e;
+    }
     switch (tile) {
+    case 6: return launch_pipe_t<16, 16, 8, S>(sa, fa, max_npix, s);
     case 1: return launch_pipe_t<8, 32, 8, S>(sa, fa, max_npix, s);
     case 3: return launch_pipe_t<8, 32, 2, S>(sa, fa, max_npix, s);
     case 4: return launch_pipe_t<32, 8, 4, S>(sa, fa, max_npix, s);
@@ -231,6 +492,7 @@ hipError_t launch_pipe_s(const SlmArgs &sa, const FuseArgs &fa, int tile, int64_
 template <int S>
 hipError_t launch_fuse_s(const FuseArgs &a, int tile, hipStream_t s)
 {
+    if (S == PSFS_NEAREST && tile == kBlockTile) return launch_fuse_block(a, s);
     const TileCfg &c = kTiles[tile];
     const int64_t nb = static_cast<int64_t>((a.nx + c.tx - 1) / c.tx) * ((a.ny + c.ty - 1) / c.ty) *
                        ((a.nz + c.kz - 1) / c.kz);
@@ -242,6 +504,7 @@ hipError_t launch_fuse_s(const FuseArgs &a, int tile, hipStream_t s)
     case 3: hipLaunchKernelGGL((fuse_kernel<8, 32, 2, S>), grid, block, 0, s, a); break;
     case 4: hipLaunchKernelGGL((fuse_kernel<32, 8, 4, S>), grid, block, 0, s, a); break;
     case 5: hipLaunchKernelGGL((fuse_kernel<16, 16, 4, S>), grid, block, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((fuse_kernel<16, 16, 8, S>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

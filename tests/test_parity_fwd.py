@@ -189,6 +189,39 @@ def test_every_tile_gives_identical_bits():
         assert torch.equal(post, outs[0][0]) and torch.equal(occ, outs[0][1])
 
 
+def test_block_tile_views_that_cannot_be_staged():
+    """The block tile's LDS-staged fusion beside views it must gather directly
+    or skip: a camera inside the grid (block corners behind it), a close
+    camera with a long focal length (boxes larger than the staging arena) and
+    a camera looking past the grid (boxes that miss the image), on a grid
+    that is ragged for the 16 x 16 x 8 blocks. Bit-identical to the column
+    tiles, and within the oracle's bounds."""
+    say("block tile: cameras inside, close to and looking past the grid")
+    cams = [S.look_at_camera((0.05, -0.1, 0.02), 300.0, 200, 150, target=(1.0, 0.3, 0.1)),
+            S.look_at_camera((1.4, 0.2, 0.3), 700.0, 640, 480),
+            S.look_at_camera((-4.0, 0.5, 1.5), 150.0, 320, 240, target=(-1.0, 3.5, 1.0)),
+            S.look_at_camera((3.5, -2.0, 1.0), 150.0, 320, 240)]
+    grid = S.Grid(50, 41, 27, np.array([-1.0, -0.82, -0.54], np.float32), np.float32(0.04))
+    body = S.make_body(np.random.default_rng(44))
+    fr = S.render_frame(15, 0, cams, grid, body, (15, 0))
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs)
+    lmap = plan.likelihood(ims)
+    block = [t for t, (tx, ty, kz) in enumerate(psfs.tiles()) if (tx, ty, kz) == (16, 16, 8)]
+    assert block, "no 16 x 16 x 8 tile"
+    plan.set_tile(0)
+    p0, o0 = plan.fuse(lmap)
+    plan.set_tile(block[0])
+    p1, o1 = plan.fuse(lmap)
+    p2, o2 = plan.reconstruct(ims)
+    torch.cuda.synchronize()
+    assert torch.equal(p0, p1) and torch.equal(o0, o1)
+    assert torch.equal(p0, p2) and torch.equal(o0, o2)
+    ref, combos = oracle_forward(fr)
+    assert_posterior_parity(p1, ref, combos=combos)
+    assert_occupancy_parity(o1, ref)
+
+
 def test_bilinear_posterior_parity():
     say("bilinear posterior")
     fr = S.config_frame(0, 2)
