@@ -81,7 +81,8 @@ def test_largest_grid_index_range():
     """A 1290^3 grid (2,146,689,000 voxels, just under the 2^31 limit the header
     states) seen by 4 views: the first and last voxels, the ends of rows and
     planes, and random voxels inside and around the body, each within 1e-5 of
-    one of the posteriors the per-voxel oracle admits; occupancy consistent."""
+    one of the posteriors the per-voxel oracle admits; occupancy consistent; the
+    block tile gives the same bits at those voxels."""
     say("forward at 1290^3 voxels x 4 views (sampled)")
     f, W, H = S.IMAGE_CLASSES[0]
     cams = S.ring_rig(4, f, W, H)
@@ -105,6 +106,13 @@ def test_largest_grid_index_range():
     t = torch.from_numpy(idx).cuda()
     gp = post.view(-1)[t].cpu().numpy().astype(np.float64)
     go = occ.view(-1)[t].cpu().numpy()
+    # the block tile (16 x 16 x 8 blocks staged in LDS) over the same index range: same bits
+    block = [k for k, shape in enumerate(psfs.tiles()) if shape == (16, 16, 8)][0]
+    plan.set_tile(block)
+    plan.reconstruct(ims, post, occ)
+    torch.cuda.synchronize()
+    assert np.array_equal(post.view(-1)[t].cpu().numpy().astype(np.float64), gp)
+    assert np.array_equal(occ.view(-1)[t].cpu().numpy(), go)
     del post, occ
     torch.cuda.empty_cache()
     maps = [O.slm(i, m, v) for i, m, v in zip(fr.images, fr.mean, fr.var)]
@@ -220,6 +228,20 @@ def test_block_tile_views_that_cannot_be_staged():
     ref, combos = oracle_forward(fr)
     assert_posterior_parity(p1, ref, combos=combos)
     assert_occupancy_parity(o1, ref)
+
+
+def test_bilinear_every_tile_gives_identical_bits():
+    fr = S.config_frame(0, 1)
+    ims, mus, vs = upload(fr)
+    plan = plan_for(fr, mus, vs, sampling=psfs.BILINEAR)
+    lmap = plan.likelihood(ims)
+    outs = []
+    for t in range(len(psfs.tiles())):
+        plan.set_tile(t)
+        outs.append(plan.fuse(lmap))
+    torch.cuda.synchronize()
+    for t, (post, occ) in enumerate(outs[1:], 1):
+        assert torch.equal(post, outs[0][0]) and torch.equal(occ, outs[0][1]), f"tile {t}"
 
 
 def test_bilinear_posterior_parity():
