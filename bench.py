@@ -568,7 +568,7 @@ def measure_c2(torch, psfs, S, T, bw, args):
                               "frac_of_measured_copy": quad_bytes / (ms_st * 1e-3) / 1e9 / bw["copy_GBs"]},
             "one_frame_step_us": ms_one * 1e3, "one_frame_tile": list(psfs.tiles()[tile]),
             "one_frame_roofline": {"kernel": "pipe_kernel" if psfs.tiles()[tile] != (16, 16, 8)
-                                   else "pipe_kernel likelihood rounds + fuse_block_kernel",
+                                   else "pipe_block_kernel",
                                    "algorithmic_bytes_per_launch": one_bytes,
                                    "frac": one_bytes / (ms_one * 1e-3) / 1e9 / HBM_PEAK_GBS},
             "bits_equal_single_frames_0_15": bits}

@@ -481,8 +481,7 @@ int psfs_batch_tune(psfs_batch *batch, void *workspace_dev, size_t workspace_byt
  * or -1 for the tuned/default choice. A tile is a workgroup of tx x ty voxel
  * columns of kz voxels each. On the 16 x 16 x 8 tile the one-frame nearest
  * paths of a plan stage each block's per-view pixel boxes in LDS and read
- * them there (psfs_pipeline_step then runs as two launches); every other
- * tile and path gathers from the maps directly. */
+ * them there; every other tile and path gathers from the maps directly. */
 int psfs_tile_count(void);
 int psfs_tile_describe(int tile, int32_t *tx, int32_t *ty, int32_t *kz);
 /* Fusion tile of a plan's one-frame paths (psfs_fuse, psfs_reconstruct,

@@ -427,6 +427,45 @@ __global__ __launch_bounds__(kSBThreads) void fuse_block_kernel(FuseArgs f)
                f.post, f.occ, arena, boxes);
 }
 
+// Likelihood maps of the next frame and block-staged fusion of the current
+// one in one launch, laid out as pipe_kernel with kSBThreads-lane workgroups:
+// likelihood rounds first (kSBThreads / 64 waves of kWavePixels pixels per
+// workgroup), then fusion rounds (one voxel block each; the blocks of one XCD
+// form one contiguous octant-ordered range). The two roles share one LDS
+// allocation, so both run four workgroups (32 waves) per CU.
+__global__ __launch_bounds__(kSBThreads) void pipe_block_kernel(SlmArgs s, FuseArgs f, PipeArgs p)
+{
+    constexpr size_t kStageBytes = (kSBThreads / 64) * sizeof(SlmStage);
+    constexpr size_t kArenaBytes = kSArena * sizeof(float);
+    __shared__ __align__(16) unsigned char lds[kStageBytes > kArenaBytes ? kStageBytes : kArenaBytes];
+    __shared__ SBox boxes[kMaxViews];
+    const int round = static_cast<int>(blockIdx.x) / kNumXcd, x = static_cast<int>(blockIdx.x) % kNumXcd;
+    if (round < p.slm_rounds) {
+        const int sb = round * kNumXcd + x;
+        if (sb >= s.n * p.slm_per_view) return;
+        const int v = sb / p.slm_per_view;
+        const SlmView &sv = s.view[v];
+        const int wave = static_cast<int>(threadIdx.x >> 6);
+        const int64_t p0 = (static_cast<int64_t>(sb - v * p.slm_per_view) * (kSBThreads / 64) + wave) * kWavePixels;
+        float *out = s.lmap + sv.map_off;
+        SlmStage *stage = reinterpret_cast<SlmStage *>(lds);
+        if (p0 + kWavePixels <= sv.npix)
+            slm_wave(sv.img, sv.mean, sv.var, out, p0, s.k0, stage[wave], s.fg, InputCheck{s.check, 1u << v});
+        else if (p0 < sv.npix)
+            slm_wave_tail(sv.img, sv.mean, sv.var, out, p0, sv.npix, s.k0, s.fg, InputCheck{s.check, 1u << v});
+    } else {
+        const int64_t blk = static_cast<int64_t>(x) * p.fuse_rounds + (round - p.slm_rounds);
+        if (blk >= p.fuse_tiles) return;
+        const uint32_t nbx = static_cast<uint32_t>((f.nx + kSBX - 1) / kSBX), nby = static_cast<uint32_t>((f.ny + kSBY - 1) / kSBY);
+        const uint32_t nbz = static_cast<uint32_t>((f.nz + kSBZ - 1) / kSBZ);
+        uint32_t bi, bj, bk;
+        octant_tile(static_cast<uint32_t>(blk), nbx, nby, nbz, bi, bj, bk);
+        const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};
+        fuse_block([&](int v) -> const ViewGeom & { return f.view[v]; }, f.n, f.lmap, gd, bi, bj, bk, f.L0, f.tau,
+                   f.post, f.occ, reinterpret_cast<float *>(lds), boxes);
+    }
+}
+
 __global__ __launch_bounds__(256) void threshold_kernel(const float *post, int64_t n, float tau, uint8_t *occ)
 {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -471,13 +510,18 @@ template <int S>
 hipError_t launch_pipe_s(const SlmArgs &sa, const FuseArgs &fa, int tile, int64_t max_npix, hipStream_t s)
 {
     if (S == PSFS_NEAREST && tile == kBlockTile) {
-        // the block kernel's LDS would cut the likelihood rounds' occupancy in
-        // a shared launch: likelihood rounds alone, then the block fusion
-        FuseArgs none = fa;
-        none.post = nullptr;
-        hipError_t e = launch_pipe_t<8, 32, 4, S>(sa, none, max_npix, s);
-        if (e == hipSuccess && fa.post) e = launch_fuse_block(fa, s);
-        return e;
+        PipeArgs p{};
+        const int64_t per_wg = (kSBThreads / 64) * kWavePixels;
+        const int64_t per_view = sa.n > 0 ? (max_npix + per_wg - 1) / per_wg : 0;
+        const int64_t tiles = fa.post ? block_count(fa) : 0;
+        p.slm_per_view = static_cast<int32_t>(per_view);
+        p.slm_rounds = static_cast<int32_t>((per_view * sa.n + kNumXcd - 1) / kNumXcd);
+        p.fuse_rounds = static_cast<int32_t>((tiles + kNumXcd - 1) / kNumXcd);
+        p.fuse_tiles = tiles;
+        const int64_t blocks = static_cast<int64_t>(p.slm_rounds + p.fuse_rounds) * kNumXcd;
+        if (blocks == 0) return hipSuccess;
+        hipLaunchKernelGGL(pipe_block_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kSBThreads), 0, s, sa, fa, p);
+        return hipGetLastError();
     }
     switch (tile) {
     case 6: return launch_pipe_t<16, 16, 8, S>(sa, fa, max_npix, s);
