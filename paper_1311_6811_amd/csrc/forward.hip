@@ -149,7 +149,8 @@ __global__ __launch_bounds__(TX * TY) void pipe_pair_kernel(SlmArgs s, PairImage
 // (16x16 tiles wrote 16-byte pieces, which cost 11.5 MB of partial-line
 // writes per launch at 128^3 x 8 views) and its 16-byte gathers land on
 // fewer map rows than the 8x8 columns of the 8x32 tile (per launch at that
-// size: 32x8 51.7, 16x16 52.5, 16x16x2 53.1, 8x32 56.2 us).
+// size: 32x8 51.7, 16x16 52.5, 16x16x2 53.1, 8x32 56.2 us). Inside a wave the
+// lanes hold the 32x2 columns in groups of 2x2 (quad_lane_pos).
 template <int TX, int TY, int KZ>
 __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImages qi, FuseArgs f, PipeArgs p,
                                                             QuadOut qo)
@@ -177,8 +178,9 @@ __global__ __launch_bounds__(TX * TY) void pipe_quad_kernel(SlmArgs s, QuadImage
         const uint32_t nzc = static_cast<uint32_t>((f.nz + KZ - 1) / KZ);
         uint32_t txi, tyi, zc;
         octant_tile(static_cast<uint32_t>(tile), ntx, nty, nzc, txi, tyi, zc);
-        const int i = static_cast<int>(txi) * TX + static_cast<int>(threadIdx.x % TX);
-        const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x / TX);
+        const int pos = quad_lane_pos(static_cast<int>(threadIdx.x & 63));
+        const int i = static_cast<int>(txi) * TX + (pos % TX);
+        const int j = static_cast<int>(tyi) * TY + static_cast<int>(threadIdx.x >> 6) * (64 / TX) + pos / TX;
         const GridDesc gd{f.nx, f.ny, f.nz, f.ox, f.oy, f.oz, f.h};
         float *const post[4] = {f.post, qo.post[0], qo.post[1], qo.post[2]};
         uint8_t *const occ[4] = {f.occ, qo.occ[0], qo.occ[1], qo.occ[2]};
