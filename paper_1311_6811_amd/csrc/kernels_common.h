@@ -713,6 +713,14 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
 }
 
 
+// Slab position (y * 32 + x in a wave's 32 x 2 columns) of lane l: each group
+// of 4 lanes holds 2 x 2 columns. The L1 serves a gather as one access per
+// (4-lane group, 64-byte chunk) pair, and 2 x 2 columns share chunks of a
+// quad map more often than 4 columns of one row (a CPU model of this workload:
+// 44.5 against 48.9 accesses per gather for quad maps, 37.3 against 43.1 for
+// pair maps; the four-frame fusion half 4 % faster).
+__device__ __forceinline__ int quad_lane_pos(int l) { return (((l >> 1) & 1) << 5) + 2 * (l >> 2) + (l & 1); }
+
 // Eq. 3-9 of fuse_column (nearest sampling) for two frames of one rig at
 // once, from pair maps: each voxel-view is projected once and one 8-byte load
 // brings both frames' values; each frame's logit adds its values in view
@@ -720,7 +728,7 @@ __device__ __forceinline__ void fuse_column(const Views &views, int n, const flo
 template <int TX, int KZ, class Views>
 __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, const float *lmap2, const GridDesc &a,
                                                  int i, int j, int k0, float L0, float tau, float *post_a,
-                                                 uint8_t *occ_a, float *post_b, uint8_t *occ_b)
+                                                 uint8_t *occ_a, float *post_b, uint8_t *occ_b, float *wave_stage)
 {
     const float X = a.ox + a.h * (static_cast<float>(i) + 0.5f);
     const float Y = a.oy + a.h * (static_cast<float>(j) + 0.5f);
@@ -731,8 +739,10 @@ __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, cons
         La[kk] = L0;
         Lb[kk] = L0;
     }
+    static_assert(TX == 32 && KZ == 4, "lanes hold 2 x 2 columns of a 32 x 2 slab, 4 voxels each");
     const int lane = static_cast<int>(threadIdx.x & 63);
-    const int i_lo = i - (lane % TX), j_lo = j - (lane / TX);
+    const int pos = quad_lane_pos(lane);
+    const int i_lo = i - (pos % TX), j_lo = j - (pos / TX);
     const uint32_t inside = wave_inside_mask(views, n, a, i_lo, i_lo + TX - 1, j_lo, j_lo + 64 / TX - 1, k0,
                                              k0 + KZ - 1);
     for (int v = 0; v < n; ++v) {
@@ -769,6 +779,44 @@ __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, cons
             Lb[kk] += val[kk].y;
         }
     }
+    // A wave whose 32 x 2 x 4 voxels all lie in the grid, with rows that start
+    // 16-byte aligned, regroups both frames' outputs through LDS and stores
+    // whole 16-byte pieces of rows non-temporally, as fuse_column_quad does.
+    bool aligned_rows = (a.nx & 15) == 0;
+    for (const void *q : {static_cast<const void *>(post_a), static_cast<const void *>(post_b),
+                          static_cast<const void *>(occ_a), static_cast<const void *>(occ_b)})
+        aligned_rows = aligned_rows && (reinterpret_cast<uintptr_t>(q) & 15) == 0;
+    if (aligned_rows && i_lo + 31 < a.nx && j_lo + 1 < a.ny && k0 + KZ - 1 < a.nz) {
+        // stage entry (f * KZ + kk) * 64 + pos: voxel (i_lo + pos % 32, j_lo + pos / 32, k0 + kk), frame f
+        uint8_t *stage_b = reinterpret_cast<uint8_t *>(wave_stage + 2 * KZ * 64);
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            const float pa = sigmoid_fast(La[kk]), pb = sigmoid_fast(Lb[kk]);
+            wave_stage[kk * 64 + pos] = pa;
+            wave_stage[(KZ + kk) * 64 + pos] = pb;
+            stage_b[kk * 64 + pos] = pa > tau ? 1 : 0;
+            stage_b[(KZ + kk) * 64 + pos] = pb > tau ? 1 : 0;
+        }
+        wave_lds_sync();
+        const int r = lane >> 3, c = lane & 7;           // row r = (kk, y) = (r / 2, r % 2), 16-byte piece c
+        const int64_t row = (static_cast<int64_t>(k0 + (r >> 1)) * a.ny + j_lo + (r & 1)) * a.nx + i_lo;
+        __builtin_nontemporal_store(*reinterpret_cast<const f32x4 *>(wave_stage + (r >> 1) * 64 + (r & 1) * 32 + 4 * c),
+                                    reinterpret_cast<f32x4 *>(post_a + row + 4 * c));
+        __builtin_nontemporal_store(
+            *reinterpret_cast<const f32x4 *>(wave_stage + (KZ + (r >> 1)) * 64 + (r & 1) * 32 + 4 * c),
+            reinterpret_cast<f32x4 *>(post_b + row + 4 * c));
+        if (lane < 32) {
+            // lane l: frame l / 16, row (l / 2) % 8, half l % 2 of the row's 32 bytes
+            const int f = lane >> 4, rr = (lane >> 1) & 7, half = lane & 1;
+            const int64_t orow = (static_cast<int64_t>(k0 + (rr >> 1)) * a.ny + j_lo + (rr & 1)) * a.nx + i_lo;
+            uint8_t *const dst = f == 0 ? occ_a : occ_b;
+            if (dst)
+                __builtin_nontemporal_store(
+                    *reinterpret_cast<const f32x4 *>(stage_b + (f * KZ + (rr >> 1)) * 64 + (rr & 1) * 32 + 16 * half),
+                    reinterpret_cast<f32x4 *>(dst + orow + 16 * half));
+        }
+        return;
+    }
     if (i >= a.nx || j >= a.ny) return;
     const int64_t plane = static_cast<int64_t>(a.nx) * a.ny;
     int64_t idx = (static_cast<int64_t>(k0) * a.ny + j) * a.nx + i;
@@ -789,13 +837,6 @@ __device__ __forceinline__ void fuse_column_pair(const Views &views, int n, cons
 // each frame's logit adds its values in view order, so every posterior has
 // the bits fuse_column gives that frame alone. post[f] / occ[f] are frame f's
 // outputs (occ[f] nullable).
-// Slab position (y * 32 + x in a wave's 32 x 2 columns) of lane l: each group
-// of 4 lanes holds 2 x 2 columns. The L1 serves a gather as one access per
-// (4-lane group, 64-byte chunk) pair, and 2 x 2 columns share chunks of a
-// quad map more often than 4 columns of one row (a CPU model of this workload:
-// 44.5 against 48.9 accesses per gather; the fusion half 4 % faster).
-__device__ __forceinline__ int quad_lane_pos(int l) { return (((l >> 1) & 1) << 5) + 2 * (l >> 2) + (l & 1); }
-
 template <int TX, int KZ, class Views>
 __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, const float *lmap4, const GridDesc &a,
                                                  int i, int j, int k0, float L0, float tau, float *const (&post)[4],
@@ -810,6 +851,7 @@ __device__ __forceinline__ void fuse_column_quad(const Views &views, int n, cons
 #pragma unroll
         for (int f = 0; f < 4; ++f) L[kk][f] = L0;
     }
+    static_assert(TX == 32, "lanes hold 2 x 2 columns of a 32 x 2 slab (quad_lane_pos)");
     const int lane = static_cast<int>(threadIdx.x & 63);
     const int pos = quad_lane_pos(lane);
     const int i_lo = i - (pos % TX), j_lo = j - (pos / TX);
