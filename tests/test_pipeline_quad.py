@@ -123,6 +123,21 @@ def test_quad_ragged_sequence_foreground_and_oracle():
     plan.set_foreground(None)
 
 
+def test_quad_grid_with_whole_and_partial_32_column_waves():
+    """A grid whose rows are a multiple of 16 voxels but not of 32, with
+    ragged y and z edges: waves that lie inside the grid store their outputs
+    as regrouped row pieces, the others voxel by voxel, in the same launch;
+    every frame bit-identical to the frame alone."""
+    say("four-frame sequence, 48 x 41 x 22 grid")
+    rng = np.random.default_rng(45)
+    cams = S.ring_rig(4, 300.0, 320, 240)
+    grid = S.Grid(48, 41, 22, np.array([-0.96, -0.82, -0.44], np.float32), np.float32(0.04))
+    frames = [S.render_frame(16, f, cams, grid, S.make_body(rng), (16, 0)) for f in range(8)]
+    plan, images = sequence(frames)
+    outs = run_quads(plan, images)
+    assert_frames_match(plan, images, outs)
+
+
 def test_quad_cameras_inside_and_close_to_the_grid():
     """Views whose pixel box cannot be staged: a camera inside the grid (block
     corners behind it), a close camera with a long focal length (boxes larger
