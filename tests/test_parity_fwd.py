@@ -222,9 +222,18 @@ def test_block_tile_views_that_cannot_be_staged():
     plan.set_tile(block[0])
     p1, o1 = plan.fuse(lmap)
     p2, o2 = plan.reconstruct(ims)
+    # the pipelined form: maps of the frame, then its fusion beside the maps again
+    m0, m1 = plan.new_lmap(), plan.new_lmap()
+    plan.pipeline_step(ims, m0)
+    p3, o3 = torch.full_like(p0, -1.0), torch.full_like(o0, 7)
+    plan.pipeline_step(ims, m1, m0, p3, o3)
     torch.cuda.synchronize()
     assert torch.equal(p0, p1) and torch.equal(o0, o1)
     assert torch.equal(p0, p2) and torch.equal(o0, o2)
+    assert torch.equal(p0, p3) and torch.equal(o0, o3)
+    for k in range(len(cams)):        # each view's map (the padding between views is not written)
+        assert torch.equal(plan.lmap_view(m0, k), plan.lmap_view(lmap, k))
+        assert torch.equal(plan.lmap_view(m1, k), plan.lmap_view(lmap, k))
     ref, combos = oracle_forward(fr)
     assert_posterior_parity(p1, ref, combos=combos)
     assert_occupancy_parity(o1, ref)
