@@ -229,6 +229,12 @@ def main():
         print("bench.py needs --steps >= 1, --warmup >= 0 and --replays >= 1", file=sys.stderr)
         sys.exit(2)
 
+    # the autotuners of the batch and the 256^3 one-frame leg time their tiles
+    # afresh into a cache of this run's own, unless the caller names one
+    if "PSFS_AUTOTUNE_CACHE" not in os.environ:
+        import tempfile
+        os.environ["PSFS_AUTOTUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="psfs_bench_"), "autotune.json")
+
     import torch
     import paper_1311_6811_amd as psfs
     from synth import scene as S
